@@ -1,0 +1,241 @@
+"""FP64 CPU oracle of the EMD misfit (PDHG with linesearch, Algorithm 1 of the paper).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package; the library in
+``paper_1808_07284_amd`` never does, and the two share no code.
+
+The arithmetic lives in ``emd_oracle.c`` (plain loops, double precision).  This
+module only marshals numpy arrays into it with ctypes and builds it with gcc on
+first use when the shared object is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "emd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# per-gather status codes (Section numbers refer to the paper)
+RUNNING, CONVERGED, MAX_ITER, ZERO_SOURCE, NONFINITE, LS_FAIL, MASS_IMBALANCE = range(7)
+STATUS_NAMES = ["RUNNING", "CONVERGED", "MAX_ITER", "ZERO_SOURCE", "NONFINITE",
+                "LS_FAIL", "MASS_IMBALANCE"]
+MASS_BALANCE, MASS_UNIT, MASS_NONE = 0, 1, 2
+LS_L2, LS_L1, LS_FIXED = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile emd_oracle.c into liboracle.so with gcc -O2."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("xi", C.c_double), ("zeta", C.c_double),
+                ("delta", C.c_double), ("alpha1", C.c_double),
+                ("alpha_max_factor", C.c_double), ("tol_res", C.c_double),
+                ("mass_tol", C.c_double), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("max_ls_trials", C.c_int32),
+                ("ls_mode", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("ls_trials", C.c_int32),
+                ("pad", C.c_int32), ("rel_res", C.c_double), ("emd", C.c_double),
+                ("transport", C.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = C.CDLL(build())
+        dp = C.POINTER(C.c_double)
+        lib.oracle_grad.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        lib.oracle_div.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        lib.oracle_shrink.argtypes = [C.c_double, C.c_double]
+        lib.oracle_shrink.restype = C.c_double
+        lib.oracle_prox.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        lib.oracle_prox.restype = C.c_double
+        lib.oracle_cell_measure.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double]
+        lib.oracle_cell_measure.restype = C.c_double
+        lib.oracle_lambda_bound.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double]
+        lib.oracle_lambda_bound.restype = C.c_double
+        lib.oracle_decompose.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp,
+                                         C.c_int, dp, dp, dp, dp]
+        lib.oracle_emd_value.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                         dp, dp, dp, dp]
+        lib.oracle_params_default.argtypes = [C.POINTER(_Params)]
+        lib.oracle_solve.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp,
+                                     C.POINTER(_Params), dp, dp, dp, C.POINTER(_Info), dp]
+        lib.oracle_solve.restype = C.c_int
+        lib.oracle_adjoint.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp,
+                                       dp, C.c_int, C.c_double, dp]
+        lib.oracle_misfit.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp,
+                                      C.c_int, C.POINTER(_Params), dp, dp, dp, dp,
+                                      C.POINTER(_Info)]
+        lib.oracle_misfit.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Params:
+    """Solver parameters; defaults are the paper's constants (eps = 1e-4,
+    xi = 0.5, zeta = 0.99, delta = 1e5; Section 2.2)."""
+    eps: float = 1e-4
+    xi: float = 0.5
+    zeta: float = 0.99
+    delta: float = 1e5
+    alpha1: float = 0.0
+    alpha_max_factor: float = 1e6
+    tol_res: float = 1e-5
+    mass_tol: float = 1e-6
+    max_iter: int = 100000
+    check_every: int = 10
+    max_ls_trials: int = 40
+    ls_mode: int = LS_L2
+
+    def _c(self) -> _Params:
+        return _Params(self.eps, self.xi, self.zeta, self.delta, self.alpha1,
+                       self.alpha_max_factor, self.tol_res, self.mass_tol,
+                       self.max_iter, self.check_every, self.max_ls_trials, self.ls_mode)
+
+
+@dataclass
+class SolveResult:
+    ux: np.ndarray
+    ut: np.ndarray
+    phi: np.ndarray
+    status: int
+    iters: int
+    ls_trials: int
+    rel_res: float
+    emd: float
+    transport: float
+    alpha_trace: np.ndarray | None = None
+
+
+def grad(phi, dx, dt):
+    phi = _f64(phi)
+    nr, nt = phi.shape
+    gx = np.empty_like(phi)
+    gt = np.empty_like(phi)
+    _load().oracle_grad(nr, nt, dx, dt, _p(phi), _p(gx), _p(gt))
+    return gx, gt
+
+
+def div(ux, ut, dx, dt):
+    ux = _f64(ux)
+    ut = _f64(ut)
+    nr, nt = ux.shape
+    out = np.empty_like(ux)
+    _load().oracle_div(nr, nt, dx, dt, _p(ux), _p(ut), _p(out))
+    return out
+
+
+def shrink(x, y):
+    return _load().oracle_shrink(float(x), float(y))
+
+
+def prox(u, g, alpha, eps):
+    return _load().oracle_prox(float(u), float(g), float(alpha), float(eps))
+
+
+def cell_measure(nr, nt, dx, dt):
+    return _load().oracle_cell_measure(nr, nt, dx, dt)
+
+
+def lambda_bound(nr, nt, dx, dt):
+    return _load().oracle_lambda_bound(nr, nt, dx, dt)
+
+
+def decompose(pcal, pobs, dx, dt, mass_mode=MASS_BALANCE):
+    """Returns (s, f, g, mass) with mass = (M_f, M_g, mean(Pcal - Pobs))."""
+    pcal = _f64(pcal)
+    pobs = _f64(pobs)
+    nr, nt = pcal.shape
+    s = np.empty_like(pcal)
+    f = np.empty_like(pcal)
+    g = np.empty_like(pcal)
+    mass = np.zeros(3)
+    _load().oracle_decompose(nr, nt, dx, dt, _p(pcal), _p(pobs), mass_mode, _p(s), _p(f),
+                             _p(g), _p(mass))
+    return s, f, g, mass
+
+
+def emd_value(ux, ut, dx, dt, eps=1e-4):
+    ux = _f64(ux)
+    ut = _f64(ut)
+    nr, nt = ux.shape
+    e = C.c_double()
+    w = C.c_double()
+    _load().oracle_emd_value(nr, nt, dx, dt, eps, _p(ux), _p(ut), C.byref(e), C.byref(w))
+    return e.value, w.value
+
+
+def solve(s, dx, dt, params: Params | None = None, u0=None, phi0=None,
+          trace: bool = False) -> SolveResult:
+    """Run Algorithm 1 on the source s (div u + s = 0) of one gather."""
+    params = params or Params()
+    s = _f64(s)
+    nr, nt = s.shape
+    ux = np.zeros_like(s) if u0 is None else _f64(u0[0]).copy()
+    ut = np.zeros_like(s) if u0 is None else _f64(u0[1]).copy()
+    phi = np.zeros_like(s) if phi0 is None else _f64(phi0).copy()
+    info = _Info()
+    tr = np.zeros(max(params.max_iter, 1)) if trace else None
+    _load().oracle_solve(nr, nt, dx, dt, _p(s), C.byref(params._c()), _p(ux), _p(ut), _p(phi),
+                         C.byref(info), _p(tr) if trace else None)
+    return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
+                       info.emd, info.transport,
+                       tr[:info.iters].copy() if trace else None)
+
+
+def adjoint(phi, pcal, pobs, mass, dx, dt, mass_mode=MASS_BALANCE, gbar=1.0):
+    phi = _f64(phi)
+    pcal = _f64(pcal)
+    pobs = _f64(pobs)
+    mass = _f64(mass)
+    nr, nt = phi.shape
+    psi = np.empty_like(phi)
+    _load().oracle_adjoint(nr, nt, dx, dt, _p(phi), _p(pcal), _p(pobs), _p(mass), mass_mode,
+                           float(gbar), _p(psi))
+    return psi
+
+
+def misfit(pcal, pobs, dx, dt, mass_mode=MASS_BALANCE, params: Params | None = None):
+    """decompose -> solve -> EMD for one gather.  Returns (SolveResult, mass)."""
+    params = params or Params()
+    pcal = _f64(pcal)
+    pobs = _f64(pobs)
+    nr, nt = pcal.shape
+    ux = np.zeros_like(pcal)
+    ut = np.zeros_like(pcal)
+    phi = np.zeros_like(pcal)
+    mass = np.zeros(3)
+    info = _Info()
+    _load().oracle_misfit(nr, nt, dx, dt, _p(pcal), _p(pobs), mass_mode,
+                          C.byref(params._c()), _p(ux), _p(ut), _p(phi), _p(mass),
+                          C.byref(info))
+    return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
+                       info.emd, info.transport), mass

@@ -1,0 +1,480 @@
+/*
+ * emd_oracle.c -- plain FP64 CPU reference of the EMD misfit of
+ * Yong, Liao, Huang, Li, Lin, "Misfit function for full waveform inversion based
+ * on Earth Mover's Distance with dynamic formulation" (arXiv 1808.07284).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP library is checked
+ * against.  Only the test suite, the smoke check and the benchmark's CPU baseline
+ * may load it; the library never does, and it shares no code, header or constant
+ * table with the library.
+ *
+ * It follows the paper step by step, one gather at a time, in double precision,
+ * with plain loops and no fusion:
+ *   - signed data split and recombination (Section 2.1, Mainini strategy),
+ *   - the grid and the backward-difference gradient (Section 2.2, gradient
+ *     equations); the divergence is taken as minus the transpose of that gradient
+ *     so that the adjoint identity <u, grad phi> = -<div u, phi> of Section 2.2
+ *     holds exactly (reading G1: the printed forward-difference divergence with
+ *     "0 at i = nr / j = nt" violates that identity on the boundary rows),
+ *   - the objective Phi = ||u||_{1,1} + eps/2 ||u||_2^2 and EMD = Phi dx dt
+ *     (Section 2.2),
+ *   - the closed-form primal update with the shrink operator and the dual update
+ *     (Section 2.2, primal-update / dual-update equations),
+ *   - PDHG with linesearch (Algorithm 1; Malitsky and Pock's method), recomputing
+ *     div and grad for every trial,
+ *   - the adjoint source phi (Section 2.3) chained through the source
+ *     normalisation.
+ *
+ * Readings where the paper is silent or garbled (the same list is kept in the
+ * design notes): the stop rule is the relative divergence residual
+ * ||div u + s||_2 / ||s||_2 <= tol checked every check_every iterations; the
+ * first trial step is the upper end alpha_k sqrt(1 + theta_k) of the allowed
+ * interval, capped at alpha_max_factor * alpha_1; alpha_1 defaults to
+ * (delta * lambda)^(-1/2) with lambda = 4/dx^2 + 4/dt^2 (Gershgorin bound of
+ * Section 2.2), so alpha_1 beta_1 = 1/lambda; the linesearch test uses the
+ * Euclidean norm by default (the Malitsky-Pock setting) and the printed
+ * l1 norms as an option; u and phi start at 0 unless warm-started; a gather of
+ * one receiver (or one sample) drops that axis' terms and uses a unit spacing
+ * for it in the cell measure.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* per-gather status codes (values fixed by the library's public header too) */
+enum {
+    OR_RUNNING = 0,
+    OR_CONVERGED = 1,
+    OR_MAX_ITER = 2,
+    OR_ZERO_SOURCE = 3,
+    OR_NONFINITE = 4,
+    OR_LS_FAIL = 5,
+    OR_MASS_IMBALANCE = 6
+};
+
+enum { OR_MASS_BALANCE = 0, OR_MASS_UNIT = 1, OR_MASS_NONE = 2 };
+enum { OR_LS_L2 = 0, OR_LS_L1 = 1, OR_LS_FIXED = 2 };
+
+typedef struct {
+    double eps;              /* regularisation epsilon, 1e-4 in the paper     */
+    double xi;               /* linesearch shrink factor, 0.5                 */
+    double zeta;             /* linesearch tolerance, 0.99                    */
+    double delta;            /* dual/primal step ratio beta/alpha, 1e5        */
+    double alpha1;           /* initial primal step; <= 0 selects the default */
+    double alpha_max_factor; /* cap on alpha relative to alpha_1; <= 0: none  */
+    double tol_res;          /* stop when ||div u + s|| / ||s|| <= tol_res    */
+    double mass_tol;         /* relative imbalance allowed with mass mode none */
+    int32_t max_iter;
+    int32_t check_every;
+    int32_t max_ls_trials;
+    int32_t ls_mode;         /* OR_LS_L2, OR_LS_L1 or OR_LS_FIXED             */
+} oracle_params;
+
+typedef struct {
+    int32_t status, iters, ls_trials, pad;
+    double rel_res, emd, transport;
+} oracle_info;
+
+/* ------------------------------------------------------------------ helpers */
+
+/* Cell measure dx*dt of the discrete integral (Section 2.2: EMD = Phi dx dt);
+ * an axis of length one contributes a unit factor. */
+double oracle_cell_measure(int nr, int nt, double dx, double dt)
+{
+    return (nr > 1 ? dx : 1.0) * (nt > 1 ? dt : 1.0);
+}
+
+/* Gershgorin bound of the largest eigenvalue of the discrete Laplacian
+ * div(grad): 4/dx^2 + 4/dt^2 (Section 2.2), dropping an axis of length one. */
+double oracle_lambda_bound(int nr, int nt, double dx, double dt)
+{
+    double l = 0.0;
+    if (nr > 1) l += 4.0 / (dx * dx);
+    if (nt > 1) l += 4.0 / (dt * dt);
+    return l;
+}
+
+/* ------------------------------------------------------------- operators */
+
+/* Backward-difference gradient with zero first row/column (Section 2.2):
+ *   (d_x phi)_{i,j} = (phi_{i,j} - phi_{i-1,j}) / dx  for i > 1, else 0,
+ *   (d_t phi)_{i,j} = (phi_{i,j} - phi_{i,j-1}) / dt  for j > 1, else 0.
+ * Arrays are [nr][nt], receiver index i, time index j (0-based here). */
+void oracle_grad(int nr, int nt, double dx, double dt, const double* phi,
+                 double* gx, double* gt)
+{
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j) {
+            int64_t c = (int64_t)i * nt + j;
+            gx[c] = (i > 0) ? (phi[c] - phi[c - nt]) / dx : 0.0;
+            gt[c] = (j > 0) ? (phi[c] - phi[c - 1]) / dt : 0.0;
+        }
+}
+
+/* Divergence taken as minus the transpose of oracle_grad, so that
+ * <u, grad phi> = -<div u, phi> (the adjoint identity of Section 2.2):
+ *   (div u)_{i,j} = ([i < nr] u^x_{i+1,j} - [i > 1] u^x_{i,j}) / dx
+ *                 + ([j < nt] u^t_{i,j+1} - [j > 1] u^t_{i,j}) / dt.
+ * It is a forward difference in the interior, as the paper prints; on the last
+ * row/column it is -u/dx (-u/dt), and u on the first row/column is never read. */
+void oracle_div(int nr, int nt, double dx, double dt, const double* ux,
+                const double* ut, double* out)
+{
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j) {
+            int64_t c = (int64_t)i * nt + j;
+            double ax = 0.0, at = 0.0;
+            if (i + 1 < nr) ax += ux[c + nt];
+            if (i > 0) ax -= ux[c];
+            if (j + 1 < nt) at += ut[c + 1];
+            if (j > 0) at -= ut[c];
+            out[c] = ax / dx + at / dt;
+        }
+}
+
+/* shrink(x, y) = (1 - y/|x|) x if |x| >= y, else 0 (Section 2.2). */
+double oracle_shrink(double x, double y)
+{
+    double ax = fabs(x);
+    if (ax >= y && ax > 0.0) return (1.0 - y / ax) * x;
+    return 0.0;
+}
+
+/* Closed-form primal update of one flux component (primal-update equation):
+ *   u_new = shrink(u + alpha g, alpha) / (1 + eps alpha),
+ * where g is the matching component of grad phi. */
+double oracle_prox(double u, double g, double alpha, double eps)
+{
+    return oracle_shrink(u + alpha * g, alpha) / (1.0 + eps * alpha);
+}
+
+/* ---------------------------------------------------------- decomposition */
+
+/* Mainini split and recombination (Section 2.1):
+ *   f = Pcal^+ + Pobs^-,  g = Pobs^+ + Pcal^-,  so f - g = Pcal - Pobs,
+ * masses M_f = dx dt sum f, M_g = dx dt sum g, and the source s that the solver
+ * consumes (div u + s = 0):
+ *   balance: s = (Pcal - Pobs) - mean(Pcal - Pobs)   (adds uniform mass to the
+ *            lighter side; identical to the paper when the masses balance),
+ *   unit:    s = f / M_f - g / M_g                    (both normalised to mass 1),
+ *   none:    s = Pcal - Pobs                           (the paper as printed).
+ * mass[0] = M_f, mass[1] = M_g, mass[2] = mean(Pcal - Pobs).
+ * f and g may be NULL.  Sums use Neumaier compensation. */
+typedef struct { double s, c; } or_acc;
+static void acc_add(or_acc* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double acc_val(const or_acc* a) { return a->s + a->c; }
+
+void oracle_decompose(int nr, int nt, double dx, double dt, const double* pcal,
+                      const double* pobs, int mass_mode, double* s, double* f,
+                      double* g, double* mass)
+{
+    int64_t n = (int64_t)nr * nt;
+    double cm = oracle_cell_measure(nr, nt, dx, dt);
+    or_acc sf = {0, 0}, sg = {0, 0}, sd = {0, 0};
+    for (int64_t c = 0; c < n; ++c) {
+        double fp = fmax(pcal[c], 0.0) + fmax(-pobs[c], 0.0);
+        double gp = fmax(pobs[c], 0.0) + fmax(-pcal[c], 0.0);
+        if (f) f[c] = fp;
+        if (g) g[c] = gp;
+        acc_add(&sf, fp);
+        acc_add(&sg, gp);
+        acc_add(&sd, pcal[c] - pobs[c]);
+    }
+    double Mf = cm * acc_val(&sf), Mg = cm * acc_val(&sg);
+    double mean = acc_val(&sd) / (double)n;
+    mass[0] = Mf;
+    mass[1] = Mg;
+    mass[2] = mean;
+    for (int64_t c = 0; c < n; ++c) {
+        double d = pcal[c] - pobs[c];
+        if (mass_mode == OR_MASS_BALANCE) {
+            s[c] = d - mean;
+        } else if (mass_mode == OR_MASS_UNIT) {
+            double fp = fmax(pcal[c], 0.0) + fmax(-pobs[c], 0.0);
+            double gp = fmax(pobs[c], 0.0) + fmax(-pcal[c], 0.0);
+            s[c] = (Mf > 0 ? fp / Mf : 0.0) - (Mg > 0 ? gp / Mg : 0.0);
+        } else {
+            s[c] = d;
+        }
+    }
+}
+
+/* --------------------------------------------------------------- objective */
+
+/* EMD = dx dt (||u||_{1,1} + eps/2 ||u||_2^2) and the transport part
+ * W = dx dt ||u||_{1,1} (Section 2.2, objective and its scaling). */
+void oracle_emd_value(int nr, int nt, double dx, double dt, double eps,
+                      const double* ux, const double* ut, double* emd,
+                      double* transport)
+{
+    int64_t n = (int64_t)nr * nt;
+    or_acc l1 = {0, 0}, l2 = {0, 0};
+    for (int64_t c = 0; c < n; ++c) {
+        acc_add(&l1, fabs(ux[c]) + fabs(ut[c]));
+        acc_add(&l2, ux[c] * ux[c] + ut[c] * ut[c]);
+    }
+    double cm = oracle_cell_measure(nr, nt, dx, dt);
+    *emd = cm * (acc_val(&l1) + 0.5 * eps * acc_val(&l2));
+    *transport = cm * acc_val(&l1);
+}
+
+static double norm_l2(int64_t n, const double* a)
+{
+    double t = 0.0;
+    for (int64_t c = 0; c < n; ++c) t += a[c] * a[c];
+    return sqrt(t);
+}
+
+/* ----------------------------------------------------------------- solver */
+
+void oracle_params_default(oracle_params* p)
+{
+    p->eps = 1e-4;
+    p->xi = 0.5;
+    p->zeta = 0.99;
+    p->delta = 1e5;
+    p->alpha1 = 0.0;
+    p->alpha_max_factor = 1e6;
+    p->tol_res = 1e-5;
+    p->mass_tol = 1e-6;
+    p->max_iter = 100000;
+    p->check_every = 10;
+    p->max_ls_trials = 40;
+    p->ls_mode = OR_LS_L2;
+}
+
+/* PDHG with linesearch for min Phi(u) s.t. div u + s = 0 (Algorithm 1).
+ *
+ * In/out: ux, ut, phi ([nr][nt] each) hold the start point (zeros for a cold
+ * start) and receive the final iterates.  alpha_trace, if not NULL, receives the
+ * accepted step alpha_{k+1} of every iteration (max_iter entries).
+ * Iteration k (from the paper):
+ *   u^{k+1} = shrink(u^k + alpha_k grad phi^k, alpha_k) / (1 + eps alpha_k)
+ *   pick alpha in [alpha_k, alpha_k sqrt(1 + theta_k)], then repeat
+ *       theta = alpha / alpha_k,  beta = delta alpha,
+ *       ubar = u^{k+1} + theta (u^{k+1} - u^k),
+ *       phi^{k+1} = phi^k + beta (div ubar + s),
+ *   shrinking alpha by xi until
+ *       sqrt(delta) alpha ||grad phi^{k+1} - grad phi^k|| <= zeta ||phi^{k+1} - phi^k||.
+ * (The paper multiplies alpha by xi before the test and compares against
+ * xi zeta; the factors cancel, so the test is on the trial alpha itself.) */
+int oracle_solve(int nr, int nt, double dx, double dt, const double* s,
+                 const oracle_params* p, double* ux, double* ut, double* phi,
+                 oracle_info* info, double* alpha_trace)
+{
+    int64_t n = (int64_t)nr * nt;
+    memset(info, 0, sizeof(*info));
+    double snorm = norm_l2(n, s);
+    if (!isfinite(snorm)) {
+        info->status = OR_NONFINITE;
+        info->emd = NAN;
+        info->transport = NAN;
+        info->rel_res = NAN;
+        return info->status;
+    }
+    if (snorm == 0.0) {
+        memset(ux, 0, sizeof(double) * n);
+        memset(ut, 0, sizeof(double) * n);
+        memset(phi, 0, sizeof(double) * n);
+        info->status = OR_ZERO_SOURCE;
+        return info->status;
+    }
+
+    double lam = oracle_lambda_bound(nr, nt, dx, dt);
+    double alpha_k = (p->alpha1 > 0.0) ? p->alpha1 : 1.0 / sqrt(p->delta * lam);
+    double alpha_max = (p->alpha_max_factor > 0.0) ? p->alpha_max_factor * alpha_k : INFINITY;
+    double theta_k = 1.0;
+    const int l1 = (p->ls_mode == OR_LS_L1);
+    const int fixed = (p->ls_mode == OR_LS_FIXED);
+    const double dx_eff = (nr > 1) ? dx : 1.0, dt_eff = (nt > 1) ? dt : 1.0;
+
+    double* gx = malloc(sizeof(double) * n);   /* grad phi^k            */
+    double* gt = malloc(sizeof(double) * n);
+    double* uxn = malloc(sizeof(double) * n);  /* u^{k+1}               */
+    double* utn = malloc(sizeof(double) * n);
+    double* ubx = malloc(sizeof(double) * n);  /* ubar                  */
+    double* ubt = malloc(sizeof(double) * n);
+    double* dv = malloc(sizeof(double) * n);   /* div ubar, div u       */
+    double* phin = malloc(sizeof(double) * n); /* trial phi^{k+1}       */
+    double* gnx = malloc(sizeof(double) * n);  /* grad of trial phi     */
+    double* gnt = malloc(sizeof(double) * n);
+
+    int status = OR_RUNNING;
+    int iters = 0;
+    long trials_total = 0;
+    double rel_res = NAN;
+
+    while (status == OR_RUNNING) {
+        /* primal step: closed-form prox of the objective at phi^k */
+        oracle_grad(nr, nt, dx_eff, dt_eff, phi, gx, gt);
+        for (int64_t c = 0; c < n; ++c) {
+            uxn[c] = oracle_prox(ux[c], gx[c], alpha_k, p->eps);
+            utn[c] = oracle_prox(ut[c], gt[c], alpha_k, p->eps);
+        }
+
+        /* linesearch on the dual step */
+        double alpha = fixed ? alpha_k : alpha_k * sqrt(1.0 + theta_k);
+        if (alpha > alpha_max) alpha = alpha_max;
+        double theta = 1.0;
+        int trials = 0;
+        for (;;) {
+            theta = fixed ? 1.0 : alpha / alpha_k;
+            double beta = p->delta * alpha;
+            for (int64_t c = 0; c < n; ++c) {
+                ubx[c] = uxn[c] + theta * (uxn[c] - ux[c]);
+                ubt[c] = utn[c] + theta * (utn[c] - ut[c]);
+            }
+            oracle_div(nr, nt, dx_eff, dt_eff, ubx, ubt, dv);
+            for (int64_t c = 0; c < n; ++c) phin[c] = phi[c] + beta * (dv[c] + s[c]);
+            if (fixed) break;
+            oracle_grad(nr, nt, dx_eff, dt_eff, phin, gnx, gnt);
+            double dphi = 0.0, dgrad = 0.0;
+            for (int64_t c = 0; c < n; ++c) {
+                double e = phin[c] - phi[c];
+                double ex = gnx[c] - gx[c], et = gnt[c] - gt[c];
+                if (l1) {
+                    dphi += fabs(e);
+                    dgrad += fabs(ex) + fabs(et);
+                } else {
+                    dphi += e * e;
+                    dgrad += ex * ex + et * et;
+                }
+            }
+            if (!l1) {
+                dphi = sqrt(dphi);
+                dgrad = sqrt(dgrad);
+            }
+            if (!isfinite(dphi) || !isfinite(dgrad)) {
+                status = OR_NONFINITE;
+                break;
+            }
+            if (sqrt(p->delta) * alpha * dgrad <= p->zeta * dphi) break;
+            alpha *= p->xi;
+            ++trials;
+            if (trials > p->max_ls_trials) {
+                status = OR_LS_FAIL;
+                break;
+            }
+        }
+        trials_total += trials;
+        if (status != OR_RUNNING) break;
+
+        /* accept the iterate */
+        memcpy(ux, uxn, sizeof(double) * n);
+        memcpy(ut, utn, sizeof(double) * n);
+        memcpy(phi, phin, sizeof(double) * n);
+        alpha_k = alpha;
+        theta_k = theta;
+        if (alpha_trace) alpha_trace[iters] = alpha;
+        ++iters;
+
+        /* stop rule: relative divergence residual of the current flux */
+        if (iters % p->check_every == 0 || iters == p->max_iter) {
+            oracle_div(nr, nt, dx_eff, dt_eff, ux, ut, dv);
+            for (int64_t c = 0; c < n; ++c) dv[c] += s[c];
+            rel_res = norm_l2(n, dv) / snorm;
+            if (!isfinite(rel_res)) status = OR_NONFINITE;
+            else if (iters % p->check_every == 0 && rel_res <= p->tol_res) status = OR_CONVERGED;
+            else if (iters == p->max_iter) status = OR_MAX_ITER;
+        }
+    }
+
+    oracle_div(nr, nt, dx_eff, dt_eff, ux, ut, dv);
+    for (int64_t c = 0; c < n; ++c) dv[c] += s[c];
+    info->rel_res = norm_l2(n, dv) / snorm;
+    oracle_emd_value(nr, nt, dx, dt, p->eps, ux, ut, &info->emd, &info->transport);
+    info->status = status;
+    info->iters = iters;
+    info->ls_trials = (int32_t)trials_total;
+
+    free(gx); free(gt); free(uxn); free(utn); free(ubx); free(ubt);
+    free(dv); free(phin); free(gnx); free(gnt);
+    return status;
+}
+
+/* ------------------------------------------------------------------ adjoint */
+
+/* Adjoint source psi = d EMD / d Pcal (Section 2.3: the dual variable phi is the
+ * derivative of the misfit with respect to the source term), scaled by the
+ * upstream gradient gbar and chained through the source normalisation:
+ *   d EMD / d s = dx dt phi  (EMD = dx dt Phi, and phi multiplies s in the
+ *                             Lagrangian),
+ *   balance: psi = dx dt (phi - mean phi) gbar,
+ *   unit:    psi_n = dx dt [H_n (phi_n - pf) / M_f + (1 - H_n)(phi_n - pg) / M_g] gbar,
+ *            pf = <phi, f> / sum f,  pg = <phi, g> / sum g,  H_n = [Pcal_n > 0],
+ *   none:    psi = dx dt phi gbar.
+ * mass is the triple written by oracle_decompose. */
+void oracle_adjoint(int nr, int nt, double dx, double dt, const double* phi,
+                    const double* pcal, const double* pobs, const double* mass,
+                    int mass_mode, double gbar, double* psi)
+{
+    int64_t n = (int64_t)nr * nt;
+    double cm = oracle_cell_measure(nr, nt, dx, dt);
+    if (mass_mode == OR_MASS_BALANCE) {
+        or_acc a = {0, 0};
+        for (int64_t c = 0; c < n; ++c) acc_add(&a, phi[c]);
+        double mean = acc_val(&a) / (double)n;
+        for (int64_t c = 0; c < n; ++c) psi[c] = cm * (phi[c] - mean) * gbar;
+    } else if (mass_mode == OR_MASS_UNIT) {
+        or_acc pf = {0, 0}, pg = {0, 0}, sf = {0, 0}, sg = {0, 0};
+        for (int64_t c = 0; c < n; ++c) {
+            double fp = fmax(pcal[c], 0.0) + fmax(-pobs[c], 0.0);
+            double gp = fmax(pobs[c], 0.0) + fmax(-pcal[c], 0.0);
+            acc_add(&pf, phi[c] * fp);
+            acc_add(&pg, phi[c] * gp);
+            acc_add(&sf, fp);
+            acc_add(&sg, gp);
+        }
+        double mf = acc_val(&sf) > 0 ? acc_val(&pf) / acc_val(&sf) : 0.0;
+        double mg = acc_val(&sg) > 0 ? acc_val(&pg) / acc_val(&sg) : 0.0;
+        double Mf = mass[0], Mg = mass[1];
+        for (int64_t c = 0; c < n; ++c) {
+            double h = pcal[c] > 0.0 ? 1.0 : 0.0;
+            double a = (Mf > 0 ? h * (phi[c] - mf) / Mf : 0.0) +
+                       (Mg > 0 ? (1.0 - h) * (phi[c] - mg) / Mg : 0.0);
+            psi[c] = cm * a * gbar;
+        }
+    } else {
+        for (int64_t c = 0; c < n; ++c) psi[c] = cm * phi[c] * gbar;
+    }
+}
+
+/* --------------------------------------------------------- whole misfit */
+
+/* decompose -> solve -> EMD for one gather, the sequence a caller of the misfit
+ * runs (Section 2.1 then Algorithm 1).  With mass mode none and masses that
+ * differ by more than mass_tol (relative), the problem is infeasible: status
+ * MASS_IMBALANCE, EMD = NaN, u = phi = 0. */
+int oracle_misfit(int nr, int nt, double dx, double dt, const double* pcal,
+                  const double* pobs, int mass_mode, const oracle_params* p,
+                  double* ux, double* ut, double* phi, double* mass,
+                  oracle_info* info)
+{
+    int64_t n = (int64_t)nr * nt;
+    double* s = malloc(sizeof(double) * n);
+    oracle_decompose(nr, nt, dx, dt, pcal, pobs, mass_mode, s, NULL, NULL, mass);
+    int st;
+    if (mass_mode == OR_MASS_NONE &&
+        fabs(mass[0] - mass[1]) > p->mass_tol * fmax(mass[0], mass[1])) {
+        memset(info, 0, sizeof(*info));
+        memset(ux, 0, sizeof(double) * n);
+        memset(ut, 0, sizeof(double) * n);
+        memset(phi, 0, sizeof(double) * n);
+        info->status = OR_MASS_IMBALANCE;
+        info->emd = NAN;
+        info->transport = NAN;
+        info->rel_res = NAN;
+        st = info->status;
+    } else {
+        st = oracle_solve(nr, nt, dx, dt, s, p, ux, ut, phi, info, NULL);
+    }
+    free(s);
+    return st;
+}
