@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the EMD misfit hot path on one MI355X.
+
+A step is the whole path over one batch of synthetic gathers already resident in
+HBM: emd_decompose -> emd_pdhg_solve (PDHG with linesearch, every gather run to
+the relative-residual stop rule) -> emd_adjoint_source.  The metric is PDHG
+cell-updates per second (sum over gathers of nr * nt * iterations, divided by the
+step time) for the batched FP32 solve; the plain FP64 solve of the same batch, one
+gather per launch sequence, is timed beside it, and their EMDs are compared.
+
+Default workload: 64 gathers, nt ~ U{1500..3000}, nr ~ U{200..500}, 4-8 hyperbolic
+events (seed 3).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi, R
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from synth import config2_gather, config3_batch, config4_batch, config5_batch
+    if name == "c3":
+        return config3_batch(), "64 gathers, nt~U{1500..3000} x nr~U{200..500}, 4-8 hyperbolic events, seed 3"
+    if name == "c2":
+        return [config2_gather()], "1 gather, nt=2000 x nr=400, 6 hyperbolic events, seed 2"
+    if name == "c4":
+        return config4_batch(), "32 gathers, nt=2000 x nr=300, seed 4"
+    if name == "c5":
+        return config5_batch(), "16 gathers, nt=4000 x nr=1600, 10 events + direct arrival, seed 5"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_step(E, plan, pcal, pobs, bufs):
+    s, mass = E.emd_decompose(plan, pcal, pobs, s_out=bufs["s"], mass_out=bufs["mass"])
+    emd, phi, _, info = E.emd_pdhg_solve(plan, s, phi=bufs["phi"], mass=mass,
+                                         emd_out=bufs["emd"], info_out=bufs["info"])
+    E.emd_adjoint_source(plan, phi, pcal, pobs, mass, psi_out=bufs["psi"])
+    return emd, info
+
+
+def cpu_baseline(gathers, iters, threads):
+    """The FP64 oracle, as it stands, on a bounded sample: `threads` gathers of the
+    workload, `iters` fixed iterations each, one gather per host thread."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build()
+    sample = gathers[:threads]
+    srcs = []
+    for g in sample:
+        s, _, _, _ = oracle.decompose(g.pcal.astype(np.float64), g.pobs.astype(np.float64), g.dx, g.dt)
+        srcs.append((s, g))
+    p = oracle.Params(max_iter=iters, tol_res=0.0, check_every=iters)
+
+    def one(item):
+        s, g = item
+        r = oracle.solve(s, g.dx, g.dt, p)
+        return g.cells * r.iters
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        cu = sum(ex.map(one, srcs))
+    el = time.perf_counter() - t0
+    return {"value": cu / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} gathers of the workload ({sum(g.cells for g in sample)} cells), "
+                      f"{iters} fixed PDHG-linesearch iterations each, one gather per thread, "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--tol", type=float, default=1e-5, help="relative residual stop rule")
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--rows", type=int, default=0, help="rows per tile (0: plan default)")
+    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the batch shards by gather across GPUs, not built here)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1808_07284_amd as E
+    from synth import pack_batch
+
+    gathers, wdesc = workload(args.workload)
+    cells = sum(g.cells for g in gathers)
+    log(f"workload {args.workload}: {len(gathers)} gathers, {cells} cells")
+    pcal_h, pobs_h, desc = pack_batch(gathers, np.float32)
+    dev = torch.device("cuda", 0)
+    pcal = torch.from_numpy(pcal_h).to(dev)
+    pobs = torch.from_numpy(pobs_h).to(dev)
+    params = E.SolverParams(precision=E.F32, tol_res=args.tol, max_iter=args.max_iter)
+    plan = E.Plan(desc, len(pcal_h), params)
+    if args.rows:
+        plan.set_tiling(args.rows)
+    bufs = {"s": plan.empty(), "phi": plan.empty(), "psi": plan.empty(),
+            "mass": torch.empty(len(gathers), 3, dtype=torch.float64, device=dev),
+            "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
+            "info": torch.empty(len(gathers) * 48, dtype=torch.uint8, device=dev)}
+
+    for w in range(args.warmup):
+        run_step(E, plan, pcal, pobs, bufs)
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
+
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    cell_updates = 0
+    sweep_ms = 0.0
+    sweeps = 0
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        emd, info = run_step(E, plan, pcal, pobs, bufs)
+        q = plan.query()
+        cell_updates += q["last_cell_updates"]
+        sweep_ms += q["last_sweep_ms"]
+        sweeps += q["last_sweeps"]
+        log(f"step {k}: {q['last_sweeps']} sweeps, {q['last_sweep_ms']:.1f} ms in sweeps")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = cell_updates / (ms / 1e3)
+    inf = E.info_numpy(info)
+    emd32 = emd.cpu().numpy().copy()
+    log(f"f32: {value:.3e} cell-updates/s, {ms_per_step:.1f} ms/step (wall {wall:.1f} s), "
+        f"iters min/mean/max {inf['iters'].min()}/{inf['iters'].mean():.0f}/{inf['iters'].max()}, "
+        f"statuses {np.bincount(inf['status'], minlength=7).tolist()}")
+
+    # dominant kernel: the fused sweep; algorithmic bytes per launch = 36 B x cells
+    # updated in that launch, timed with HIP events the library records on this stream
+    algo_bytes = BYTES_PER_CELL_ITER["f32"] * cell_updates
+    achieved = algo_bytes / (sweep_ms / 1e3) / 1e9 if sweep_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep<float>", "launches": int(sweeps),
+                "avg_launch_us": round(sweep_ms * 1e3 / max(sweeps, 1), 2),
+                "algo_bytes_per_launch": int(algo_bytes / max(sweeps, 1))}
+
+    extra = {}
+    if not args.no_f64:
+        # plain FP64 solve of the same batch, one gather per plan, to the same stop rule
+        p64 = E.SolverParams(precision=E.F64, tol_res=args.tol, max_iter=args.max_iter)
+        pc64 = pcal.double()
+        po64 = pobs.double()
+        emd64 = np.zeros(len(gathers))
+        cu64 = 0
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        for k, (nr, nt, dx, dt, off) in enumerate(desc):
+            pl = E.Plan([(nr, nt, dx, dt, 0)], nr * nt, p64)
+            a = pc64[off:off + nr * nt]
+            b = po64[off:off + nr * nt]
+            s, mass = E.emd_decompose(pl, a, b)
+            e, phi, _, inf64 = E.emd_pdhg_solve(pl, s, mass=mass)
+            E.emd_adjoint_source(pl, phi, a, b, mass)
+            cu64 += pl.query()["last_cell_updates"]
+            emd64[k] = float(e.cpu()[0])
+            pl.close()
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t64
+        rel = np.abs(emd32 - emd64) / np.abs(emd64)
+        extra["plain_f64"] = {"value": cu64 / el64, "unit": "cell-updates/s", "seconds": round(el64, 2),
+                              "speedup_f32_batched": round(value / (cu64 / el64), 2),
+                              "emd_rel_diff_max": float(rel.max()), "emd_rel_diff_median": float(np.median(rel))}
+        log(f"plain f64: {cu64 / el64:.3e} cell-updates/s in {el64:.1f} s; "
+            f"EMD rel diff max {rel.max():.2e} median {np.median(rel):.2e}")
+
+    cpu = None
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(gathers, args.cpu_iters, threads)
+        log(f"cpu oracle: {cpu['value']:.3e} cell-updates/s on {threads} threads")
+
+    out = {"metric": "PDHG cell-updates/s to 1e-5 rel EMD err, batched FP32 vs plain FP64; % HBM peak",
+           "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wdesc, "gathers": len(gathers), "cells": cells,
+                      "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
+                      "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max())},
+           "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

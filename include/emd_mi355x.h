@@ -1,0 +1,224 @@
+/*
+ * emd_mi355x.h -- C ABI of the MI355X (gfx950) library for the Earth Mover's
+ * Distance misfit between predicted and observed seismic shot gathers, in the
+ * dynamic (Beckmann) form solved by primal-dual hybrid gradient with linesearch.
+ *
+ * Method: Yong, Liao, Huang, Li, Lin, "Misfit function for full waveform
+ * inversion based on Earth Mover's Distance with dynamic formulation"
+ * (arXiv 1808.07284).  Section 2.1 gives the signed-data recombination, Section
+ * 2.2 the grid, the difference operators, the objective
+ * Phi = ||u||_{1,1} + eps/2 ||u||_2^2 with EMD = Phi dx dt, the closed-form
+ * primal/dual updates and Algorithm 1 (PDHG with linesearch); Section 2.3 makes
+ * the dual potential phi the adjoint source of full waveform inversion.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  A batch holds `ngather` gathers.  Gather g is a dense row-major array
+ *   [nr][nt] (receiver index i, time index j contiguous: the paper's (i, j)),
+ *   starting `offset` elements into each batch buffer.  Element type is float in
+ *   EMD_F32 precision and double in EMD_F64 precision, for every field buffer.
+ *   The flux u is two such batches back to back: u^x at [0, N) and u^t at
+ *   [N, 2N), N = the batch length given to emd_plan_create.
+ * Operators.  grad is the backward difference with a zero first row/column
+ *   (Section 2.2); div is minus its transpose, the forward difference of Section
+ *   2.2 in the interior, -u/dx (-u/dt) on the last row (column), so that the
+ *   adjoint identity <u, grad phi> = -<div u, phi> of Section 2.2 holds exactly.
+ *   The constraint is div u + s = 0, s = Pcal - Pobs after normalisation (the
+ *   paper's div u + Pcal - Pobs = 0), and the adjoint source is +phi.
+ * Memory.  Every data pointer is a device pointer owned by the caller; the library
+ *   never frees or retains it past the call.  The plan owns its workspace
+ *   (padded solver state, per-gather scalars, reduction partials).
+ * Streams.  Work is enqueued on `stream` (0 = the null stream).  emd_decompose
+ *   and emd_adjoint_source never synchronise.  emd_pdhg_solve synchronises the
+ *   stream once per `sweeps_per_sync` iterations to read the number of finished
+ *   gathers (one 4-byte read), unless `max_iter` caps the solve first.
+ * Errors.  A call returns EMD_SUCCESS or an error code; emd_last_error() gives a
+ *   message (per thread).  Bad arguments are reported before anything is
+ *   enqueued.  Numerical outcomes are per-gather statuses (EMD_GATHER_*) in the
+ *   emd_solve_info array, never call failures.
+ * Device.  Calls run on the current HIP device, which must be the gfx950 device
+ *   the plan was created on.
+ */
+#ifndef EMD_MI355X_H
+#define EMD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t emd_status;
+
+/* call status */
+#define EMD_SUCCESS 0
+#define EMD_ERR_INVALID_ARGUMENT 1 /* a size, spacing, mode or parameter is out of range */
+#define EMD_ERR_NULL_POINTER 2     /* a required pointer is NULL                        */
+#define EMD_ERR_DEVICE 3           /* the current device is not gfx950 / not the plan's */
+#define EMD_ERR_HIP 4              /* a HIP runtime call failed                         */
+#define EMD_ERR_OUT_OF_MEMORY 5    /* workspace allocation failed                       */
+#define EMD_ERR_UNSUPPORTED 6      /* valid request that this build does not implement  */
+
+/* per-gather solve status, written into emd_solve_info.status */
+#define EMD_GATHER_RUNNING 0
+#define EMD_GATHER_CONVERGED 1      /* ||div u + s||_2 / ||s||_2 <= tol_res at a check   */
+#define EMD_GATHER_MAX_ITER 2       /* max_iter iterations done without converging      */
+#define EMD_GATHER_ZERO_SOURCE 3    /* s == 0: EMD = 0, u = phi = 0, no iteration        */
+#define EMD_GATHER_NONFINITE 4      /* NaN/Inf in the source or during the iteration    */
+#define EMD_GATHER_LS_FAIL 5        /* more than max_ls_trials backtracking steps       */
+#define EMD_GATHER_MASS_IMBALANCE 6 /* mass mode none and |M_f - M_g| > mass_tol max M  */
+
+typedef enum { EMD_MASS_BALANCE = 0, EMD_MASS_UNIT = 1, EMD_MASS_NONE = 2 } emd_mass_mode;
+typedef enum { EMD_LS_L2 = 0, EMD_LS_L1 = 1, EMD_LS_FIXED = 2 } emd_ls_mode;
+typedef enum { EMD_F32 = 0, EMD_F64 = 1 } emd_precision;
+
+/* One gather of the batch (host array passed to emd_plan_create).
+ * nr, nt >= 1; dx, dt > 0 are the spacings of the EMD grid (Section 2.2:
+ * dx = X/(nr - 1), dt = T/(nt - 1)); an axis of length one drops its difference
+ * terms and contributes 1 to the cell measure dx dt.  offset >= 0 is the element
+ * offset of the gather in every batch buffer; gathers must not overlap. */
+typedef struct {
+    int32_t nr, nt;
+    double dx, dt;
+    int64_t offset;
+} emd_gather_desc;
+
+/* Solver parameters.  emd_params_default() fills the paper's constants:
+ * eps = 1e-4 (Section 2.2), xi = 0.5, zeta = 0.99, delta = 1e5 (parameters of
+ * Algorithm 1), theta_1 = 1.
+ *   alpha1 <= 0 selects alpha_1 = (delta lambda)^(-1/2), lambda = 4/dx^2 + 4/dt^2
+ *     the Gershgorin bound of Section 2.2, so that alpha_1 beta_1 = 1/lambda.
+ *   alpha_max_factor > 0 caps every step at alpha_max_factor * alpha_1.
+ *   tol_res: stop when ||div u + s||_2 / ||s||_2 <= tol_res, checked every
+ *     check_every iterations (this certifies feasibility, not optimality).
+ *   ls_mode: EMD_LS_L2 uses Euclidean norms in the linesearch test (the
+ *     Malitsky-Pock setting); EMD_LS_L1 the l1 norms printed in Algorithm 1
+ *     (returns EMD_ERR_UNSUPPORTED in this build); EMD_LS_FIXED is plain PDHG with
+ *     theta = 1 and the fixed steps alpha_1, beta_1 = delta alpha_1.
+ *   mass_mode: how emd_decompose builds s (see there) and emd_adjoint_source chains.
+ *   precision: element type of all field buffers (EMD_F32: float fields, FP64
+ *     reductions and scalars; EMD_F64: double throughout).
+ *   sweeps_per_sync: iterations enqueued between reads of the finished count. */
+typedef struct {
+    double eps, xi, zeta, delta, alpha1, alpha_max_factor, tol_res, mass_tol;
+    int32_t max_iter, check_every, max_ls_trials, ls_mode;
+    int32_t mass_mode, precision, sweeps_per_sync, reserved;
+} emd_params;
+
+/* Per-gather result (device array written by emd_pdhg_solve). */
+typedef struct {
+    int32_t status;    /* EMD_GATHER_*                                    */
+    int32_t iters;     /* accepted PDHG iterations                        */
+    int32_t ls_trials; /* backtracking steps over the whole solve         */
+    int32_t pad;
+    double rel_res;    /* ||div u + s||_2 / ||s||_2 of the returned u      */
+    double emd;        /* dx dt (||u||_{1,1} + eps/2 ||u||_2^2)            */
+    double transport;  /* dx dt ||u||_{1,1}                                */
+    double alpha;      /* last accepted primal step                        */
+} emd_solve_info;
+
+/* Plan statistics (host struct filled by emd_plan_query). */
+typedef struct {
+    int32_t ngather, tiles, rows_per_tile, samples_per_tile;
+    int64_t batch_len;        /* N                                             */
+    int64_t cells;            /* sum of nr * nt                                */
+    int64_t workspace_bytes;  /* device memory owned by the plan               */
+    int64_t last_sweeps;      /* sweep launches of the last emd_pdhg_solve     */
+    int64_t last_cell_updates;/* sum over gathers of nr * nt * iterations      */
+    double last_sweep_ms;     /* GPU time from the first to the last sweep     */
+} emd_plan_stats;
+
+typedef struct emd_plan emd_plan;
+
+/* Fill *p with the defaults above (max_iter 100000, check_every 10,
+ * max_ls_trials 40, tol_res 1e-5, alpha_max_factor 1e6, mass_tol 1e-6,
+ * sweeps_per_sync 64, EMD_LS_L2, EMD_MASS_BALANCE, EMD_F32). */
+emd_status emd_params_default(emd_params* p);
+
+/* Create a plan for `ngather` gathers described by the host array h_desc, in a
+ * batch of `batch_len` elements, on the current device.  Validates every
+ * descriptor and parameter, copies them, and allocates the workspace (about
+ * 7 field copies of the padded batch plus per-tile scalars).  *out receives the
+ * plan; it is NULL on failure. */
+emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64_t batch_len,
+                           const emd_params* p, emd_plan** out);
+
+/* Release the plan and its workspace (synchronises the device first). NULL is a no-op. */
+emd_status emd_plan_destroy(emd_plan* plan);
+
+/* Replace the solver parameters of an existing plan (precision must not change). */
+emd_status emd_plan_set_params(emd_plan* plan, const emd_params* p);
+
+/* Choose the tile height (receiver rows per wavefront tile, 1..1024) used by the
+ * solver sweeps; 0 restores the plan's default.  Used by the autotuner. */
+emd_status emd_plan_set_tiling(emd_plan* plan, int32_t rows_per_tile);
+
+/* Fill *out with the plan's sizes and the counters of its last solve. */
+emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out);
+
+/* Signed-data recombination and mass normalisation (Section 2.1).
+ *   f = Pcal^+ + Pobs^-, g = Pobs^+ + Pcal^- (so f - g = Pcal - Pobs),
+ *   d_mass[3 g + 0] = M_f = dx dt sum f,  d_mass[3 g + 1] = M_g = dx dt sum g,
+ *   d_mass[3 g + 2] = mean(Pcal - Pobs)   (FP64 sums in a fixed order),
+ *   s_out = (Pcal - Pobs) - mean(Pcal - Pobs)  (EMD_MASS_BALANCE),
+ *         = f / M_f - g / M_g                  (EMD_MASS_UNIT),
+ *         = Pcal - Pobs                        (EMD_MASS_NONE).
+ * pcal, pobs, s_out: batch buffers of the plan's precision; f_out, g_out: optional
+ * batch buffers (NULL to skip); d_mass: device double[3 ngather].  s_out must not
+ * alias pcal or pobs. */
+emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, void* s_out,
+                         void* f_out, void* g_out, double* d_mass, hipStream_t stream);
+
+/* Solve min Phi(u) s.t. div u + s = 0 for every gather by PDHG with linesearch
+ * (Algorithm 1, Section 2.2), all gathers in one batch of fused sweeps.
+ *   s: source batch (from emd_decompose).
+ *   u: optional flux, 2 batches [u^x | u^t]; read as the start point when
+ *      warm_start != 0, and receives the final flux (NULL: cold start, not returned).
+ *   phi: dual potential batch; read as the start point when warm_start != 0, and
+ *      receives the final potential (required: it is the adjoint source).
+ *   d_mass: optional device double[3 ngather] from emd_decompose; with
+ *      EMD_MASS_NONE it flags gathers whose masses differ (MASS_IMBALANCE).
+ *   d_emd: optional device double[ngather] receiving the EMD values.
+ *   d_info: optional device emd_solve_info[ngather]. */
+emd_status emd_pdhg_solve(emd_plan* plan, const void* s, void* u, void* phi, int32_t warm_start,
+                          const double* d_mass, double* d_emd, emd_solve_info* d_info,
+                          hipStream_t stream);
+
+/* The same solve with the step sizes taken from a schedule instead of the
+ * linesearch: iteration k of gather g uses alpha_{k+1} = d_alpha[g * ld_alpha + k]
+ * (theta_{k+1} = alpha_{k+1} / alpha_k, beta_{k+1} = delta alpha_{k+1}) and
+ * counts no backtracking.  Replaying the accepted steps of another solve of the
+ * same problem reproduces its iterates up to rounding; the stop rule and
+ * max_iter (<= ld_alpha) apply as usual. */
+emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* phi,
+                                 int32_t warm_start, const double* d_alpha, int32_t ld_alpha,
+                                 double* d_emd, emd_solve_info* d_info, hipStream_t stream);
+
+/* Adjoint source psi = d EMD / d Pcal (Section 2.3: the dual potential phi is the
+ * derivative of the misfit with respect to the data), chained through the mass
+ * normalisation and scaled by the upstream gradient gbar_g:
+ *   EMD_MASS_BALANCE: psi = dx dt gbar (phi - mean phi),
+ *   EMD_MASS_UNIT:    psi = dx dt gbar [H (phi - pf)/M_f + (1 - H)(phi - pg)/M_g],
+ *                     pf = <phi, f>/sum f, pg = <phi, g>/sum g, H = [Pcal > 0],
+ *   EMD_MASS_NONE:    psi = dx dt gbar phi.
+ * phi, psi_out: batch buffers; pcal, pobs: needed for EMD_MASS_UNIT only (else may
+ * be NULL); d_mass: from emd_decompose (needed for EMD_MASS_UNIT); d_gbar: optional
+ * device double[ngather] (NULL means 1).  psi_out must not alias any input. */
+emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal,
+                              const void* pobs, const double* d_mass, const double* d_gbar,
+                              void* psi_out, hipStream_t stream);
+
+/* Human-readable name of a call status. */
+const char* emd_status_string(emd_status status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* emd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMD_MI355X_H */

@@ -1,0 +1,231 @@
+"""Python binding of the C ABI (argument marshalling only; every step runs in the
+HIP kernels of libemd_mi355x.so).
+
+Tensors are torch device tensors holding a batch in the ABI layout: gather g is a
+dense [nr][nt] block at element ``offset`` of a flat buffer (see ``pack_batch`` in
+the synthetic-data package for one way to build it).  Work is enqueued on torch's
+current stream of the tensors' device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, fields
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("ls_trials", "<i4"), ("pad", "<i4"),
+                       ("rel_res", "<f8"), ("emd", "<f8"), ("transport", "<f8"), ("alpha", "<f8")])
+
+
+@dataclass
+class SolverParams:
+    """Mirror of emd_params; the defaults are the paper's constants (Section 2.2:
+    eps = 1e-4; Algorithm 1: xi = 0.5, zeta = 0.99, delta = 1e5)."""
+    eps: float = 1e-4
+    xi: float = 0.5
+    zeta: float = 0.99
+    delta: float = 1e5
+    alpha1: float = 0.0
+    alpha_max_factor: float = 1e6
+    tol_res: float = 1e-5
+    mass_tol: float = 1e-6
+    max_iter: int = 100000
+    check_every: int = 10
+    max_ls_trials: int = 40
+    ls_mode: int = L.LS_L2
+    mass_mode: int = L.MASS_BALANCE
+    precision: int = L.F32
+    sweeps_per_sync: int = 64
+
+    def to_c(self) -> L.Params:
+        p = L.Params()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        p.reserved = 0
+        return p
+
+    @classmethod
+    def library_default(cls) -> "SolverParams":
+        p = L.Params()
+        L.check(L.load().emd_params_default(C.byref(p)))
+        return cls(**{f.name: getattr(p, f.name) for f in fields(cls)})
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return torch.float64 if self.precision == L.F64 else torch.float32
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """An emd_plan: workspace and tiling for one batch of gathers.
+
+    descs: sequence of (nr, nt, dx, dt, offset); batch_len: elements per batch buffer."""
+
+    def __init__(self, descs, batch_len: int, params: SolverParams | None = None,
+                 device: int | torch.device | None = None):
+        self.params = params or SolverParams()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        arr = (L.GatherDesc * len(descs))()
+        for k, (nr, nt, dx, dt, off) in enumerate(descs):
+            arr[k] = L.GatherDesc(int(nr), int(nt), float(dx), float(dt), int(off))
+        self.descs = [tuple(d) for d in descs]
+        self.ngather = len(descs)
+        self.batch_len = int(batch_len)
+        self._h = C.c_void_p()
+        lib = L.load()
+        with torch.cuda.device(self.device):
+            L.check(lib.emd_plan_create(arr, self.ngather, self.batch_len,
+                                        C.byref(self.params.to_c()), C.byref(self._h)))
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            L.load().emd_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: SolverParams):
+        with torch.cuda.device(self.device):
+            L.check(L.load().emd_plan_set_params(self.handle, C.byref(params.to_c())))
+        self.params = params
+
+    def set_tiling(self, rows_per_tile: int):
+        with torch.cuda.device(self.device):
+            L.check(L.load().emd_plan_set_tiling(self.handle, int(rows_per_tile)))
+
+    def query(self) -> dict:
+        s = L.PlanStats()
+        L.check(L.load().emd_plan_query(self.handle, C.byref(s)))
+        return {f[0]: getattr(s, f[0]) for f in L.PlanStats._fields_}
+
+    def empty(self, *lead) -> torch.Tensor:
+        return torch.zeros(*lead, self.batch_len, dtype=self.params.dtype, device=self.device)
+
+    def _check(self, t, name, lead=()):
+        if t is None:
+            return
+        if t.device != self.device or t.dtype != self.params.dtype or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous {self.params.dtype} tensor on "
+                             f"{self.device}, got {t.dtype} on {t.device}")
+        if t.numel() != int(np.prod(lead, dtype=np.int64)) * self.batch_len:
+            raise ValueError(f"{name}: expected {lead + (self.batch_len,)} elements")
+
+
+def emd_decompose(plan: Plan, pcal, pobs, s_out=None, f_out=None, g_out=None, mass_out=None):
+    """Mainini recombination and mass normalisation (Section 2.1).
+    Returns (s, mass) with mass[g] = (M_f, M_g, mean(Pcal - Pobs))."""
+    s_out = plan.empty() if s_out is None else s_out
+    mass_out = (torch.empty(plan.ngather, 3, dtype=torch.float64, device=plan.device)
+                if mass_out is None else mass_out)
+    for t, n in ((pcal, "pcal"), (pobs, "pobs"), (s_out, "s_out"), (f_out, "f_out"), (g_out, "g_out")):
+        plan._check(t, n)
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_decompose(plan.handle, _ptr(pcal), _ptr(pobs), _ptr(s_out), _ptr(f_out),
+                                       _ptr(g_out), _ptr(mass_out), _stream(plan.device)))
+    return s_out, mass_out
+
+
+def emd_pdhg_solve(plan: Plan, s, phi=None, u=None, warm_start=False, mass=None, emd_out=None,
+                   info_out=None):
+    """PDHG with linesearch for every gather (Algorithm 1).
+    Returns (emd [ngather] float64, phi, u or None, info uint8 [ngather * 48])."""
+    phi = plan.empty() if phi is None else phi
+    emd_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
+               if emd_out is None else emd_out)
+    info_out = (torch.empty(plan.ngather * INFO_DTYPE.itemsize, dtype=torch.uint8, device=plan.device)
+                if info_out is None else info_out)
+    plan._check(s, "s")
+    plan._check(phi, "phi")
+    plan._check(u, "u", (2,))
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_pdhg_solve(plan.handle, _ptr(s), _ptr(u), _ptr(phi), int(bool(warm_start)),
+                                        _ptr(mass), _ptr(emd_out), _ptr(info_out),
+                                        _stream(plan.device)))
+    return emd_out, phi, u, info_out
+
+
+def emd_pdhg_solve_replay(plan: Plan, s, alpha, phi=None, u=None, warm_start=False, emd_out=None,
+                          info_out=None):
+    """The solve with the accepted steps alpha [ngather, ld] (float64) replayed."""
+    phi = plan.empty() if phi is None else phi
+    emd_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
+               if emd_out is None else emd_out)
+    info_out = (torch.empty(plan.ngather * INFO_DTYPE.itemsize, dtype=torch.uint8, device=plan.device)
+                if info_out is None else info_out)
+    if alpha.dtype != torch.float64 or alpha.dim() != 2 or alpha.shape[0] != plan.ngather:
+        raise ValueError("alpha must be a float64 [ngather, ld] tensor")
+    alpha = alpha.contiguous()
+    plan._check(s, "s")
+    plan._check(phi, "phi")
+    plan._check(u, "u", (2,))
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_pdhg_solve_replay(plan.handle, _ptr(s), _ptr(u), _ptr(phi),
+                                               int(bool(warm_start)), _ptr(alpha),
+                                               int(alpha.shape[1]), _ptr(emd_out), _ptr(info_out),
+                                               _stream(plan.device)))
+    return emd_out, phi, u, info_out
+
+
+def emd_adjoint_source(plan: Plan, phi, pcal=None, pobs=None, mass=None, gbar=None, psi_out=None):
+    """Adjoint source psi = d EMD / d Pcal (Section 2.3), scaled by gbar [ngather]."""
+    psi_out = plan.empty() if psi_out is None else psi_out
+    for t, n in ((phi, "phi"), (pcal, "pcal"), (pobs, "pobs"), (psi_out, "psi_out")):
+        plan._check(t, n)
+    if gbar is not None:
+        gbar = gbar.to(device=plan.device, dtype=torch.float64).contiguous()
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_adjoint_source(plan.handle, _ptr(phi), _ptr(pcal), _ptr(pobs), _ptr(mass),
+                                            _ptr(gbar), _ptr(psi_out), _stream(plan.device)))
+    return psi_out
+
+
+def info_numpy(info: torch.Tensor) -> np.ndarray:
+    """Per-gather emd_solve_info records as a numpy structured array."""
+    return np.frombuffer(info.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
+
+
+class EMDMisfit(torch.autograd.Function):
+    """EMD misfit of a batch: forward = decompose + PDHG solve, returning the EMD of
+    every gather; backward = the hand-written adjoint-source kernel (the dual
+    potential chained through the normalisation, Section 2.3).  No gradient flows
+    to the observed data."""
+
+    @staticmethod
+    def forward(ctx, pcal, pobs, plan: Plan):
+        s, mass = emd_decompose(plan, pcal, pobs)
+        emd, phi, _, info = emd_pdhg_solve(plan, s, mass=mass)
+        ctx.plan = plan
+        ctx.info = info
+        ctx.save_for_backward(phi, pcal, pobs, mass)
+        return emd.clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        phi, pcal, pobs, mass = ctx.saved_tensors
+        psi = emd_adjoint_source(ctx.plan, phi, pcal, pobs, mass, gbar=grad_out)
+        return psi, None, None
+
+
+def emd_misfit(pcal, pobs, plan: Plan):
+    return EMDMisfit.apply(pcal, pobs, plan)

@@ -1,0 +1,654 @@
+// emd_abi.hip -- host implementation of the C ABI declared in include/emd_mi355x.h.
+//
+// A plan owns the solver workspace for one batch of gathers: the padded,
+// double-buffered solver fields, the tile table, per-gather metadata and scalar
+// state, and the reduction partials.  emd_pdhg_solve enqueues one fused sweep per
+// PDHG iteration for the whole batch (replayed from a captured HIP graph in chunks
+// of sweeps_per_sync launches) and reads the finished-gather count between chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "emd_internal.h"
+#include "emd_launch.h"
+#include "emd_mi355x.h"
+
+using namespace emd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+emd_status fail(emd_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(EMD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kDefaultRows = 32;
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct emd_plan {
+    int device = -1;
+    int32_t ngather = 0;
+    int64_t batch_len = 0;
+    emd_params params{};
+    std::vector<emd_gather_desc> desc;
+    size_t elem = 4;          // bytes per field element
+    int vec = 4;              // elements per lane vector
+    int rows = kDefaultRows;  // receiver rows per tile
+    int64_t padded_len = 0;
+    int32_t ntiles = 0;
+    int grid = 0;             // blocks per tile-table launch (multiple of 8)
+    int64_t cells = 0;
+
+    // device memory
+    GatherMeta* d_meta = nullptr;
+    Tile* d_tiles = nullptr;
+    void* d_fields = nullptr;  // one allocation: s, ux[2], ut[2], phi[2], R[2]
+    double* d_part = nullptr;  // [2][tiles][NPART]
+    GState* d_gst = nullptr;   // [2][ngather]
+    int32_t* d_done = nullptr;
+    double* d_adj = nullptr;   // [ngather][4]
+    int32_t* h_done = nullptr; // pinned
+    int64_t workspace_bytes = 0;
+
+    // captured chunk of sweeps (rebuilt when the arguments change)
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    std::vector<unsigned char> graph_key;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t last_sweeps = 0;
+    int64_t last_cell_updates = 0;
+    bool timing_valid = false;
+    std::vector<emd_gather_desc> host_meta_cache;
+};
+
+namespace {
+
+emd_status check_device(emd_plan* plan)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (plan && dev != plan->device)
+        return fail(EMD_ERR_DEVICE, "current device differs from the plan's device");
+    return EMD_SUCCESS;
+}
+
+emd_status validate_params(const emd_params* p)
+{
+    if (!p) return fail(EMD_ERR_NULL_POINTER, "params is NULL");
+    auto bad = [](const char* what) { return fail(EMD_ERR_INVALID_ARGUMENT, what); };
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return bad("eps must be finite and >= 0");
+    if (!(p->xi > 0.0 && p->xi < 1.0)) return bad("xi must lie in (0, 1)");
+    if (!(p->zeta > 0.0 && p->zeta < 1.0)) return bad("zeta must lie in (0, 1)");
+    if (!(p->delta > 0.0) || !std::isfinite(p->delta)) return bad("delta must be finite and > 0");
+    if (!std::isfinite(p->alpha1)) return bad("alpha1 must be finite");
+    if (!std::isfinite(p->alpha_max_factor)) return bad("alpha_max_factor must be finite");
+    if (!(p->tol_res >= 0.0)) return bad("tol_res must be >= 0");
+    if (!(p->mass_tol >= 0.0)) return bad("mass_tol must be >= 0");
+    if (p->max_iter < 1) return bad("max_iter must be >= 1");
+    if (p->check_every < 1) return bad("check_every must be >= 1");
+    if (p->max_ls_trials < 0 || p->max_ls_trials > 1000) return bad("max_ls_trials must lie in [0, 1000]");
+    if (p->ls_mode < EMD_LS_L2 || p->ls_mode > EMD_LS_FIXED) return bad("unknown ls_mode");
+    if (p->mass_mode < EMD_MASS_BALANCE || p->mass_mode > EMD_MASS_NONE) return bad("unknown mass_mode");
+    if (p->precision != EMD_F32 && p->precision != EMD_F64) return bad("unknown precision");
+    if (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096)
+        return bad("sweeps_per_sync must lie in [2, 4096]");
+    if (p->ls_mode == EMD_LS_L1)
+        return fail(EMD_ERR_UNSUPPORTED, "the l1 linesearch test is not implemented on the GPU");
+    return EMD_SUCCESS;
+}
+
+void destroy_graph(emd_plan* plan)
+{
+    if (plan->graph) {
+        (void)hipGraphExecDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    plan->graph_key.clear();
+    plan->graph_chunk = 0;
+}
+
+// Tile table: per gather, time tiles of 62 * vec samples by row strips of `rows`,
+// ordered (gather, time tile, strip) so that strips sharing halo rows are
+// neighbours in the table (and therefore on the same XCD).
+emd_status build_tiles(emd_plan* plan)
+{
+    const int span = OUT_LANES * plan->vec;
+    std::vector<Tile> tiles;
+    std::vector<GatherMeta> meta(plan->ngather);
+    int64_t poff = 0;
+    for (int g = 0; g < plan->ngather; ++g) {
+        const emd_gather_desc& d = plan->desc[g];
+        GatherMeta& m = meta[g];
+        m.nr = d.nr;
+        m.nt = d.nt;
+        m.ld = (int32_t)round_up(d.nt, 4);
+        m.poff = poff;
+        m.uoff = d.offset;
+        m.dx = d.dx;
+        m.dt = d.dt;
+        m.cm = (d.nr > 1 ? d.dx : 1.0) * (d.nt > 1 ? d.dt : 1.0);
+        double lam = 0.0;
+        if (d.nr > 1) lam += 4.0 / (d.dx * d.dx);
+        if (d.nt > 1) lam += 4.0 / (d.dt * d.dt);
+        m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
+                                             : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
+        m.tile_base = (int32_t)tiles.size();
+        m.pad0 = 0;
+        const int ntt = (d.nt + span - 1) / span;
+        const int nst = (d.nr + plan->rows - 1) / plan->rows;
+        for (int tt = 0; tt < ntt; ++tt)
+            for (int st = 0; st < nst; ++st) tiles.push_back(Tile{g, st * plan->rows, tt * span, 0});
+        m.ntiles = (int32_t)tiles.size() - m.tile_base;
+        poff += round_up((int64_t)d.nr * m.ld, 64);
+    }
+    if (tiles.size() > (size_t)INT32_MAX / 8) return fail(EMD_ERR_INVALID_ARGUMENT, "too many tiles");
+    const bool realloc_tiles = (int32_t)tiles.size() != plan->ntiles || !plan->d_tiles;
+    plan->ntiles = (int32_t)tiles.size();
+    plan->padded_len = poff;
+    const int blocks = (plan->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    plan->grid = (int)round_up(blocks, 8);
+    if (realloc_tiles) {
+        if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+        if (plan->d_part) (void)hipFree(plan->d_part);
+        plan->d_tiles = nullptr;
+        plan->d_part = nullptr;
+        if (hipMalloc(&plan->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
+            hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * tiles.size()) != hipSuccess)
+            return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate the tile table");
+    }
+    if (!plan->d_meta && hipMalloc(&plan->d_meta, sizeof(GatherMeta) * plan->ngather) != hipSuccess)
+        return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate gather metadata");
+    HIP_TRY(hipMemcpy(plan->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(plan->d_meta, meta.data(), sizeof(GatherMeta) * meta.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(plan->d_part, 0, sizeof(double) * NPART * 2 * tiles.size()));
+    destroy_graph(plan);
+    return EMD_SUCCESS;
+}
+
+template <typename T>
+T* field(emd_plan* plan, int k)
+{
+    return reinterpret_cast<T*>(plan->d_fields) + (int64_t)k * plan->padded_len;
+}
+
+SolveScalars scalars(const emd_plan* plan, int ls_mode, const double* replay, int ld_replay)
+{
+    SolveScalars sc;
+    sc.eps = plan->params.eps;
+    sc.xi = plan->params.xi;
+    sc.zeta = plan->params.zeta;
+    sc.delta = plan->params.delta;
+    sc.tol_res = plan->params.tol_res;
+    sc.max_iter = plan->params.max_iter;
+    sc.check_every = plan->params.check_every;
+    sc.max_ls_trials = plan->params.max_ls_trials;
+    sc.ls_mode = ls_mode;
+    sc.replay = replay;
+    sc.ld_replay = ld_replay;
+    sc.pad = 0;
+    return sc;
+}
+
+template <typename T>
+AuxArgs<T> aux_args(emd_plan* plan)
+{
+    AuxArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.meta = plan->d_meta;
+    a.tiles = plan->d_tiles;
+    a.ntiles = plan->ntiles;
+    a.rows = plan->rows;
+    a.ngather = plan->ngather;
+    a.mass_mode = plan->params.mass_mode;
+    a.mass_tol = plan->params.mass_tol;
+    a.batch_len = plan->batch_len;
+    a.s_pad = field<T>(plan, 0);
+    for (int b = 0; b < 2; ++b) {
+        a.ux[b] = field<T>(plan, 1 + b);
+        a.ut[b] = field<T>(plan, 3 + b);
+        a.phi[b] = field<T>(plan, 5 + b);
+        a.R[b] = field<T>(plan, 7 + b);
+    }
+    a.part = plan->d_part;
+    a.gst = plan->d_gst;
+    a.done = plan->d_done;
+    a.adj = plan->d_adj;
+    a.eps = plan->params.eps;
+    a.alpha_max_factor = plan->params.alpha_max_factor;
+    return a;
+}
+
+template <typename T>
+SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
+{
+    SweepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.meta = plan->d_meta;
+    a.tiles = plan->d_tiles;
+    a.ntiles = plan->ntiles;
+    a.rows = plan->rows;
+    a.s = field<T>(plan, 0);
+    for (int b = 0; b < 2; ++b) {
+        a.ux[b] = field<T>(plan, 1 + b);
+        a.ut[b] = field<T>(plan, 3 + b);
+        a.phi[b] = field<T>(plan, 5 + b);
+        a.R[b] = field<T>(plan, 7 + b);
+        a.part[b] = plan->d_part + (int64_t)b * plan->ntiles * NPART;
+        a.gst[b] = plan->d_gst + (int64_t)b * plan->ngather;
+    }
+    a.done = plan->d_done;
+    a.sc = sc;
+    return a;
+}
+
+// Enqueue `count` (even) sweeps starting at parity 0.  Uses a captured graph of
+// sweeps_per_sync launches when count equals that chunk size.
+template <typename T>
+emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int count, hipStream_t stream)
+{
+    const int chunk = plan->params.sweeps_per_sync;
+    if (count == chunk) {
+        std::vector<unsigned char> key(sizeof(a));
+        std::memcpy(key.data(), &a, sizeof(a));
+        if (!plan->graph || plan->graph_chunk != chunk || plan->graph_key != key) {
+            destroy_graph(plan);
+            hipStream_t cs;
+            HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, plan->grid, cs);
+                e = hipStreamEndCapture(cs, &g);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cs);
+            if (e != hipSuccess) {
+                plan->graph = nullptr;
+                return fail(EMD_ERR_HIP, std::string("graph capture of the sweeps failed: ") +
+                                             hipGetErrorString(e));
+            }
+            plan->graph_chunk = chunk;
+            plan->graph_key = key;
+        }
+        HIP_TRY(hipGraphLaunch(plan->graph, stream));
+        return EMD_SUCCESS;
+    }
+    for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, plan->grid, stream);
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
+template <typename T>
+emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int warm,
+                      const double* d_mass, const double* replay, int ld_replay, double* d_emd,
+                      emd_solve_info* d_info, hipStream_t stream)
+{
+    AuxArgs<T> a = aux_args<T>(plan);
+    a.s_user = static_cast<const T*>(s);
+    a.u_user_in = warm ? static_cast<const T*>(u) : nullptr;
+    a.phi_user_in = warm ? static_cast<const T*>(phi) : nullptr;
+    a.u_user_out = static_cast<T*>(u);
+    a.phi_user_out = static_cast<T*>(phi);
+    a.mass = d_mass;
+    a.emd_out = d_emd;
+    a.info_out = d_info;
+
+    launch_zero_counter(plan->d_done, stream);
+    launch_copy_in<T>(a, warm, plan->grid, stream);
+    launch_gather_init<T>(a, stream);
+    HIP_TRY(hipGetLastError());
+
+    const int ls_mode = replay ? LS_REPLAY : plan->params.ls_mode;
+    const SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
+    const int chunk = plan->params.sweeps_per_sync;
+    // a gather needs iters + 1 sweeps; the last one applies the final dual step
+    const int64_t max_sweeps = round_up((int64_t)plan->params.max_iter + 2, 2);
+    int64_t sweeps = 0;
+    HIP_TRY(hipEventRecord(plan->ev0, stream));
+    for (;;) {
+        // the finished count before any sweep (gathers with nothing to solve)
+        HIP_TRY(hipMemcpyAsync(plan->h_done, plan->d_done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (*plan->h_done >= plan->ngather || sweeps >= max_sweeps) break;
+        const int count = (int)std::min<int64_t>(chunk, max_sweeps - sweeps);
+        emd_status st = enqueue_sweeps<T>(plan, sa, count, stream);
+        if (st != EMD_SUCCESS) return st;
+        sweeps += count;
+    }
+    HIP_TRY(hipEventRecord(plan->ev1, stream));
+    plan->last_sweeps = sweeps;
+    plan->timing_valid = true;
+
+    a.gst = plan->d_gst;  // parity 0: every chunk has an even number of sweeps
+    launch_finalize<T>(a, stream);
+    launch_copy_out<T>(a, plan->grid, stream);
+    HIP_TRY(hipGetLastError());
+
+    // cell updates of the solve, for the plan statistics
+    std::vector<GState> st(plan->ngather);
+    HIP_TRY(hipMemcpyAsync(st.data(), plan->d_gst, sizeof(GState) * plan->ngather, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    int64_t cu = 0;
+    for (int g = 0; g < plan->ngather; ++g) cu += (int64_t)plan->desc[g].nr * plan->desc[g].nt * st[g].iters;
+    plan->last_cell_updates = cu;
+    return EMD_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+emd_status emd_params_default(emd_params* p)
+{
+    if (!p) return fail(EMD_ERR_NULL_POINTER, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->eps = 1e-4;
+    p->xi = 0.5;
+    p->zeta = 0.99;
+    p->delta = 1e5;
+    p->alpha1 = 0.0;
+    p->alpha_max_factor = 1e6;
+    p->tol_res = 1e-5;
+    p->mass_tol = 1e-6;
+    p->max_iter = 100000;
+    p->check_every = 10;
+    p->max_ls_trials = 40;
+    p->ls_mode = EMD_LS_L2;
+    p->mass_mode = EMD_MASS_BALANCE;
+    p->precision = EMD_F32;
+    p->sweeps_per_sync = 64;
+    return EMD_SUCCESS;
+}
+
+emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64_t batch_len,
+                           const emd_params* p, emd_plan** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(EMD_ERR_NULL_POINTER, "out is NULL");
+    *out = nullptr;
+    if (!h_desc) return fail(EMD_ERR_NULL_POINTER, "h_desc is NULL");
+    if (ngather < 1) return fail(EMD_ERR_INVALID_ARGUMENT, "ngather must be >= 1");
+    if (batch_len < 1) return fail(EMD_ERR_INVALID_ARGUMENT, "batch_len must be >= 1");
+    emd_status st = validate_params(p);
+    if (st != EMD_SUCCESS) return st;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    for (int g = 0; g < ngather; ++g) {
+        const emd_gather_desc& d = h_desc[g];
+        char msg[160];
+        if (d.nr < 1 || d.nt < 1 || (int64_t)d.nr * d.nt > (int64_t)1 << 31) {
+            std::snprintf(msg, sizeof msg, "gather %d: nr, nt must be >= 1 and nr*nt <= 2^31", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        if (!(d.dx > 0.0) || !(d.dt > 0.0) || !std::isfinite(d.dx) || !std::isfinite(d.dt)) {
+            std::snprintf(msg, sizeof msg, "gather %d: dx and dt must be finite and > 0", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        if (d.offset < 0 || d.offset + (int64_t)d.nr * d.nt > batch_len) {
+            std::snprintf(msg, sizeof msg, "gather %d: [offset, offset + nr*nt) outside the batch", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        spans.emplace_back(d.offset, d.offset + (int64_t)d.nr * d.nt);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return fail(EMD_ERR_INVALID_ARGUMENT, "gathers overlap");
+
+    int dev = -1;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(EMD_ERR_DEVICE, "no HIP device");
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(EMD_ERR_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+
+    emd_plan* plan = new emd_plan();
+    plan->device = dev;
+    plan->ngather = ngather;
+    plan->batch_len = batch_len;
+    plan->params = *p;
+    plan->desc.assign(h_desc, h_desc + ngather);
+    plan->elem = p->precision == EMD_F64 ? 8 : 4;
+    plan->vec = p->precision == EMD_F64 ? 2 : 4;
+    for (auto& d : plan->desc) plan->cells += (int64_t)d.nr * d.nt;
+    auto cleanup = [&](emd_status s) {
+        emd_plan_destroy(plan);
+        return s;
+    };
+    st = build_tiles(plan);
+    if (st != EMD_SUCCESS) return cleanup(st);
+    const size_t fbytes = plan->elem * (size_t)plan->padded_len * 9;
+    if (hipMalloc(&plan->d_fields, fbytes) != hipSuccess ||
+        hipMalloc(&plan->d_gst, sizeof(GState) * 2 * ngather) != hipSuccess ||
+        hipMalloc(&plan->d_done, sizeof(int32_t) * 64) != hipSuccess ||
+        hipMalloc(&plan->d_adj, sizeof(double) * 4 * ngather) != hipSuccess) {
+        std::string m = "cannot allocate the solver workspace (" + std::to_string(fbytes >> 20) + " MiB)";
+        cleanup(EMD_SUCCESS);
+        return fail(EMD_ERR_OUT_OF_MEMORY, m);
+    }
+    if (hipHostMalloc(&plan->h_done, sizeof(int32_t) * 16, hipHostMallocDefault) != hipSuccess) {
+        cleanup(EMD_SUCCESS);
+        return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate pinned host memory");
+    }
+    if (hipMemset(plan->d_fields, 0, fbytes) != hipSuccess ||
+        hipMemset(plan->d_gst, 0, sizeof(GState) * 2 * ngather) != hipSuccess ||
+        hipMemset(plan->d_done, 0, sizeof(int32_t) * 64) != hipSuccess ||
+        hipEventCreate(&plan->ev0) != hipSuccess || hipEventCreate(&plan->ev1) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        cleanup(EMD_SUCCESS);
+        return fail(EMD_ERR_HIP, "workspace initialisation failed");
+    }
+    plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
+                            (int64_t)sizeof(double) * NPART * 2 * plan->ntiles +
+                            (int64_t)sizeof(Tile) * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
+    *out = plan;
+    return EMD_SUCCESS;
+}
+
+emd_status emd_plan_destroy(emd_plan* plan)
+{
+    if (!plan) return EMD_SUCCESS;
+    (void)hipDeviceSynchronize();
+    destroy_graph(plan);
+    if (plan->d_meta) (void)hipFree(plan->d_meta);
+    if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    if (plan->d_fields) (void)hipFree(plan->d_fields);
+    if (plan->d_part) (void)hipFree(plan->d_part);
+    if (plan->d_gst) (void)hipFree(plan->d_gst);
+    if (plan->d_done) (void)hipFree(plan->d_done);
+    if (plan->d_adj) (void)hipFree(plan->d_adj);
+    if (plan->h_done) (void)hipHostFree(plan->h_done);
+    if (plan->ev0) (void)hipEventDestroy(plan->ev0);
+    if (plan->ev1) (void)hipEventDestroy(plan->ev1);
+    delete plan;
+    return EMD_SUCCESS;
+}
+
+emd_status emd_plan_set_params(emd_plan* plan, const emd_params* p)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    emd_status st = validate_params(p);
+    if (st != EMD_SUCCESS) return st;
+    if (p->precision != plan->params.precision)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "precision cannot change on an existing plan");
+    st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    plan->params = *p;
+    return build_tiles(plan);  // alpha_1 depends on delta and alpha1
+}
+
+emd_status emd_plan_set_tiling(emd_plan* plan, int32_t rows_per_tile)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (rows_per_tile < 0 || rows_per_tile > 1024)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "rows_per_tile must lie in [0, 1024]");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    plan->rows = rows_per_tile == 0 ? kDefaultRows : rows_per_tile;
+    return build_tiles(plan);
+}
+
+emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out)
+{
+    g_last_error.clear();
+    if (!plan || !out) return fail(EMD_ERR_NULL_POINTER, "plan or out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->ngather = plan->ngather;
+    out->tiles = plan->ntiles;
+    out->rows_per_tile = plan->rows;
+    out->samples_per_tile = OUT_LANES * plan->vec;
+    out->batch_len = plan->batch_len;
+    out->cells = plan->cells;
+    out->workspace_bytes = plan->workspace_bytes;
+    out->last_sweeps = plan->last_sweeps;
+    out->last_cell_updates = plan->last_cell_updates;
+    out->last_sweep_ms = 0.0;
+    if (plan->timing_valid) {
+        float ms = 0.f;
+        if (hipEventSynchronize(plan->ev1) == hipSuccess &&
+            hipEventElapsedTime(&ms, plan->ev0, plan->ev1) == hipSuccess)
+            out->last_sweep_ms = ms;
+    }
+    return EMD_SUCCESS;
+}
+
+emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, void* s_out,
+                         void* f_out, void* g_out, double* d_mass, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!pcal || !pobs || !s_out || !d_mass) return fail(EMD_ERR_NULL_POINTER, "pcal, pobs, s_out and d_mass are required");
+    if (s_out == pcal || s_out == pobs) return fail(EMD_ERR_INVALID_ARGUMENT, "s_out aliases an input");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    if (plan->params.precision == EMD_F32) {
+        AuxArgs<float> a = aux_args<float>(plan);
+        a.pcal = static_cast<const float*>(pcal);
+        a.pobs = static_cast<const float*>(pobs);
+        a.s_out = static_cast<float*>(s_out);
+        a.f_out = static_cast<float*>(f_out);
+        a.g_out = static_cast<float*>(g_out);
+        a.mass_out = d_mass;
+        launch_decompose<float>(a, plan->grid, stream);
+    } else {
+        AuxArgs<double> a = aux_args<double>(plan);
+        a.pcal = static_cast<const double*>(pcal);
+        a.pobs = static_cast<const double*>(pobs);
+        a.s_out = static_cast<double*>(s_out);
+        a.f_out = static_cast<double*>(f_out);
+        a.g_out = static_cast<double*>(g_out);
+        a.mass_out = d_mass;
+        launch_decompose<double>(a, plan->grid, stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
+emd_status emd_pdhg_solve(emd_plan* plan, const void* s, void* u, void* phi, int32_t warm_start,
+                          const double* d_mass, double* d_emd, emd_solve_info* d_info,
+                          hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!s || !phi) return fail(EMD_ERR_NULL_POINTER, "s and phi are required");
+    if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    if (plan->params.precision == EMD_F32)
+        return solve_impl<float>(plan, s, u, phi, warm_start != 0, d_mass, nullptr, 0, d_emd, d_info, stream);
+    return solve_impl<double>(plan, s, u, phi, warm_start != 0, d_mass, nullptr, 0, d_emd, d_info, stream);
+}
+
+emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* phi,
+                                 int32_t warm_start, const double* d_alpha, int32_t ld_alpha,
+                                 double* d_emd, emd_solve_info* d_info, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!s || !phi || !d_alpha) return fail(EMD_ERR_NULL_POINTER, "s, phi and d_alpha are required");
+    if (ld_alpha < plan->params.max_iter)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "ld_alpha must be >= max_iter");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    if (plan->params.precision == EMD_F32)
+        return solve_impl<float>(plan, s, u, phi, warm_start != 0, nullptr, d_alpha, ld_alpha, d_emd, d_info, stream);
+    return solve_impl<double>(plan, s, u, phi, warm_start != 0, nullptr, d_alpha, ld_alpha, d_emd, d_info, stream);
+}
+
+emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal, const void* pobs,
+                              const double* d_mass, const double* d_gbar, void* psi_out,
+                              hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!phi || !psi_out) return fail(EMD_ERR_NULL_POINTER, "phi and psi_out are required");
+    if (plan->params.mass_mode == EMD_MASS_UNIT && (!pcal || !pobs || !d_mass))
+        return fail(EMD_ERR_NULL_POINTER, "unit mass mode needs pcal, pobs and d_mass");
+    if (psi_out == phi || psi_out == pcal || psi_out == pobs)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "psi_out aliases an input");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    if (plan->params.precision == EMD_F32) {
+        AuxArgs<float> a = aux_args<float>(plan);
+        a.phi_user = static_cast<const float*>(phi);
+        a.pcal = static_cast<const float*>(pcal);
+        a.pobs = static_cast<const float*>(pobs);
+        a.mass = d_mass;
+        a.gbar = d_gbar;
+        a.psi_out = static_cast<float*>(psi_out);
+        launch_adjoint<float>(a, plan->grid, stream);
+    } else {
+        AuxArgs<double> a = aux_args<double>(plan);
+        a.phi_user = static_cast<const double*>(phi);
+        a.pcal = static_cast<const double*>(pcal);
+        a.pobs = static_cast<const double*>(pobs);
+        a.mass = d_mass;
+        a.gbar = d_gbar;
+        a.psi_out = static_cast<double*>(psi_out);
+        launch_adjoint<double>(a, plan->grid, stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
+const char* emd_status_string(emd_status status)
+{
+    switch (status) {
+    case EMD_SUCCESS: return "EMD_SUCCESS";
+    case EMD_ERR_INVALID_ARGUMENT: return "EMD_ERR_INVALID_ARGUMENT";
+    case EMD_ERR_NULL_POINTER: return "EMD_ERR_NULL_POINTER";
+    case EMD_ERR_DEVICE: return "EMD_ERR_DEVICE";
+    case EMD_ERR_HIP: return "EMD_ERR_HIP";
+    case EMD_ERR_OUT_OF_MEMORY: return "EMD_ERR_OUT_OF_MEMORY";
+    case EMD_ERR_UNSUPPORTED: return "EMD_ERR_UNSUPPORTED";
+    default: return "EMD_ERR_UNKNOWN";
+    }
+}
+
+const char* emd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

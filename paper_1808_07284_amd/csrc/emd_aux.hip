@@ -1,0 +1,428 @@
+// emd_aux.hip -- the once-per-solve passes around the PDHG sweeps: the signed-data
+// recombination and normalisation (Section 2.1 of the paper), moving the caller's
+// batch into the padded solver state and back, per-gather start-up and results,
+// and the adjoint source (Section 2.3).
+//
+// All passes use the sweep tile table: a wavefront covers `rows` receiver rows by
+// 62 * V time samples of one gather (lanes 1..62, V samples each), so per-gather
+// sums are built from per-tile partials reduced in a fixed order (deterministic).
+#include "emd_internal.h"
+#include "emd_launch.h"
+
+namespace emd {
+
+namespace {
+
+struct TileView {
+    int tid, g, r0, rend, j0, lane;
+    bool active;  // this lane owns samples in the tile
+};
+
+template <typename T>
+__device__ __forceinline__ TileView tile_view(const AuxArgs<T>& a, GatherMeta& gm, bool& ok)
+{
+    constexpr int V = Vec<T>::N;
+    TileView v;
+    v.tid = uniform(xcd_logical_block() * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    ok = v.tid < a.ntiles;
+    if (!ok) return v;
+    const Tile tl = a.tiles[v.tid];
+    v.g = uniform(tl.g);
+    gm = a.meta[v.g];
+    v.lane = threadIdx.x & (WAVE - 1);
+    v.r0 = tl.r0;
+    v.rend = min(tl.r0 + a.rows, gm.nr);
+    v.j0 = tl.c0 - V + V * v.lane;
+    v.active = (v.lane >= 1) && (v.lane <= OUT_LANES) && (v.j0 >= 0) && (v.j0 < gm.nt);
+    return v;
+}
+
+__device__ __forceinline__ void write_record(double* part, int tid, const double (&acc)[NPART])
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    double r[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) r[m] = wave_sum(acc[m]);
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) part[(int64_t)tid * NPART + m] = r[m];
+    }
+}
+
+// ------------------------------------------------------------------ solve start
+
+// s, u, phi from the caller's layout into buffer 0 of the padded state; R = 0.
+// Partials: sum s^2, count of non-finite s.
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_in(AuxArgs<T> a, int warm)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok) return;
+    double acc[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    for (int i = tv.r0; i < tv.rend; ++i) {
+        if (!tv.active) continue;
+        const int64_t pr = gm.poff + (int64_t)i * gm.ld + tv.j0;
+        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+        T sv[V], ux[V], ut[V], ph[V], z[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool in = tv.j0 + k < gm.nt;
+            sv[k] = in ? a.s_user[ur + k] : T(0);
+            ux[k] = (in && warm && a.u_user_in) ? a.u_user_in[ur + k] : T(0);
+            ut[k] = (in && warm && a.u_user_in) ? a.u_user_in[a.batch_len + ur + k] : T(0);
+            ph[k] = (in && warm && a.phi_user_in) ? a.phi_user_in[ur + k] : T(0);
+            z[k] = T(0);
+            if (in) {
+                acc[0] += double(sv[k]) * double(sv[k]);
+                acc[1] += isfinite(double(sv[k])) ? 0.0 : 1.0;
+            }
+        }
+        vstore(a.s_pad + pr, sv);
+        vstore(a.ux[0] + pr, ux);
+        vstore(a.ut[0] + pr, ut);
+        vstore(a.phi[0] + pr, ph);
+        vstore(a.R[0] + pr, z);
+    }
+    write_record(a.part, tv.tid, acc);
+}
+
+// One wavefront per gather: ||s||, start status and the parity-0 scalar state.
+template <typename T>
+__global__ __launch_bounds__(64) void k_gather_init(AuxArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const GatherMeta gm = a.meta[g];
+    double q[NPART];
+    reduce_records(a.part + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
+    GState st;
+    st.snorm = sqrt(q[0]);
+    st.alpha = gm.alpha1;
+    st.theta = 1.0;
+    st.alpha_max = a.alpha_max_factor > 0.0 ? a.alpha_max_factor * gm.alpha1 : INFINITY;
+    st.rel_res = 1.0;
+    st.emd = 0.0;
+    st.transport = 0.0;
+    st.iters = 0;
+    st.trials = 0;
+    st.started = 0;
+    st.ubuf = 0;
+    st.phibuf = 0;
+    int status = ST_RUNNING;
+    if (q[1] != 0.0 || !isfinite(st.snorm)) {
+        status = ST_NONFINITE;
+        st.rel_res = NAN;
+        st.emd = NAN;
+        st.transport = NAN;
+    } else if (a.mass_mode == MASS_NONE && a.mass != nullptr &&
+               fabs(a.mass[3 * g] - a.mass[3 * g + 1]) >
+                   a.mass_tol * fmax(a.mass[3 * g], a.mass[3 * g + 1])) {
+        status = ST_MASS_IMBALANCE;
+        st.rel_res = NAN;
+        st.emd = NAN;
+        st.transport = NAN;
+    } else if (st.snorm == 0.0) {
+        status = ST_ZERO_SOURCE;
+        st.rel_res = 0.0;
+    }
+    st.status = status;
+    if (threadIdx.x == 0) {
+        a.gst[g] = st;
+        if (status != ST_RUNNING) atomicAdd(a.done, 1);
+    }
+}
+
+__global__ void k_zero_counter(int32_t* c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = 0;
+}
+
+// ------------------------------------------------------------------ solve end
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_out(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok || !tv.active) return;
+    const GState st = a.gst[tv.g];
+    const bool zero = (st.status == ST_ZERO_SOURCE) || (st.status == ST_MASS_IMBALANCE);
+    const T* uxs = a.ux[st.ubuf];
+    const T* uts = a.ut[st.ubuf];
+    const T* phs = a.phi[st.phibuf];
+    for (int i = tv.r0; i < tv.rend; ++i) {
+        const int64_t pr = gm.poff + (int64_t)i * gm.ld + tv.j0;
+        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+        T ux[V], ut[V], ph[V];
+        vload(uxs + pr, ux);
+        vload(uts + pr, ut);
+        vload(phs + pr, ph);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (tv.j0 + k >= gm.nt) break;
+            a.phi_user_out[ur + k] = zero ? T(0) : ph[k];
+            if (a.u_user_out) {
+                a.u_user_out[ur + k] = zero ? T(0) : ux[k];
+                a.u_user_out[a.batch_len + ur + k] = zero ? T(0) : ut[k];
+            }
+        }
+    }
+}
+
+struct InfoRec {
+    int32_t status, iters, ls_trials, pad;
+    double rel_res, emd, transport, alpha;
+};
+
+template <typename T>
+__global__ void k_finalize(AuxArgs<T> a)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.ngather) return;
+    const GState st = a.gst[g];
+    if (a.emd_out) a.emd_out[g] = st.emd;
+    if (a.info_out) {
+        InfoRec r;
+        r.status = st.status;
+        r.iters = st.iters;
+        r.ls_trials = st.trials;
+        r.pad = 0;
+        r.rel_res = st.rel_res;
+        r.emd = st.emd;
+        r.transport = st.transport;
+        r.alpha = st.alpha;
+        reinterpret_cast<InfoRec*>(a.info_out)[g] = r;
+    }
+}
+
+// ------------------------------------------------------------------ decompose
+
+__device__ __forceinline__ double fpart(double pc, double po) { return fmax(pc, 0.0) + fmax(-po, 0.0); }
+__device__ __forceinline__ double gpart(double pc, double po) { return fmax(po, 0.0) + fmax(-pc, 0.0); }
+
+// partials: sum f, sum g, sum (Pcal - Pobs)
+template <typename T>
+__global__ __launch_bounds__(256) void k_decomp_sums(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok) return;
+    double acc[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    if (tv.active) {
+        for (int i = tv.r0; i < tv.rend; ++i) {
+            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (tv.j0 + k >= gm.nt) break;
+                const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
+                acc[0] += fpart(pc, po);
+                acc[1] += gpart(pc, po);
+                acc[2] += pc - po;
+            }
+        }
+    }
+    write_record(a.part, tv.tid, acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_decomp_mass(AuxArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const GatherMeta gm = a.meta[g];
+    double q[NPART];
+    reduce_records(a.part + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
+    if (threadIdx.x == 0) {
+        a.mass_out[3 * g + 0] = gm.cm * q[0];
+        a.mass_out[3 * g + 1] = gm.cm * q[1];
+        a.mass_out[3 * g + 2] = q[2] / (double(gm.nr) * double(gm.nt));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_decomp_source(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok || !tv.active) return;
+    const double Mf = a.mass_out[3 * tv.g], Mg = a.mass_out[3 * tv.g + 1];
+    const double mean = a.mass_out[3 * tv.g + 2];
+    for (int i = tv.r0; i < tv.rend; ++i) {
+        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (tv.j0 + k >= gm.nt) break;
+            const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
+            const double f = fpart(pc, po), g = gpart(pc, po);
+            double s;
+            if (a.mass_mode == MASS_BALANCE) s = (pc - po) - mean;
+            else if (a.mass_mode == MASS_UNIT) s = (Mf > 0.0 ? f / Mf : 0.0) - (Mg > 0.0 ? g / Mg : 0.0);
+            else s = pc - po;
+            a.s_out[ur + k] = T(s);
+            if (a.f_out) a.f_out[ur + k] = T(f);
+            if (a.g_out) a.g_out[ur + k] = T(g);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// partials: sum phi, <phi, f>, <phi, g>, sum f, sum g
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_sums(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok) return;
+    double acc[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    if (tv.active) {
+        for (int i = tv.r0; i < tv.rend; ++i) {
+            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (tv.j0 + k >= gm.nt) break;
+                const double ph = double(a.phi_user[ur + k]);
+                acc[0] += ph;
+                if (a.mass_mode == MASS_UNIT) {
+                    const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
+                    const double f = fpart(pc, po), g = gpart(pc, po);
+                    acc[1] += ph * f;
+                    acc[2] += ph * g;
+                    acc[3] += f;
+                    acc[4] += g;
+                }
+            }
+        }
+    }
+    write_record(a.part, tv.tid, acc);
+}
+
+// adj[4 g + 0] = scale dx dt gbar; [1] = mean phi (balance) or pf (unit); [2] = pg
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_scalars(AuxArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const GatherMeta gm = a.meta[g];
+    double q[NPART];
+    reduce_records(a.part + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
+    if (threadIdx.x == 0) {
+        const double gb = a.gbar ? a.gbar[g] : 1.0;
+        a.adj[4 * g + 0] = gm.cm * gb;
+        if (a.mass_mode == MASS_BALANCE) {
+            a.adj[4 * g + 1] = q[0] / (double(gm.nr) * double(gm.nt));
+            a.adj[4 * g + 2] = 0.0;
+        } else if (a.mass_mode == MASS_UNIT) {
+            a.adj[4 * g + 1] = q[3] > 0.0 ? q[1] / q[3] : 0.0;
+            a.adj[4 * g + 2] = q[4] > 0.0 ? q[2] / q[4] : 0.0;
+        } else {
+            a.adj[4 * g + 1] = 0.0;
+            a.adj[4 * g + 2] = 0.0;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_apply(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok || !tv.active) return;
+    const double scale = a.adj[4 * tv.g], c1 = a.adj[4 * tv.g + 1], c2 = a.adj[4 * tv.g + 2];
+    const double Mf = a.mass ? a.mass[3 * tv.g] : 0.0, Mg = a.mass ? a.mass[3 * tv.g + 1] : 0.0;
+    for (int i = tv.r0; i < tv.rend; ++i) {
+        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (tv.j0 + k >= gm.nt) break;
+            const double ph = double(a.phi_user[ur + k]);
+            double v;
+            if (a.mass_mode == MASS_BALANCE) {
+                v = scale * (ph - c1);
+            } else if (a.mass_mode == MASS_UNIT) {
+                const double h = double(a.pcal[ur + k]) > 0.0 ? 1.0 : 0.0;
+                v = scale * ((Mf > 0.0 ? h * (ph - c1) / Mf : 0.0) +
+                             (Mg > 0.0 ? (1.0 - h) * (ph - c2) / Mg : 0.0));
+            } else {
+                v = scale * ph;
+            }
+            a.psi_out[ur + k] = T(v);
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_copy_in(const AuxArgs<T>& a, int warm, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_copy_in<T>, dim3(grid), dim3(256), 0, stream, a, warm);
+}
+
+template <typename T>
+void launch_gather_init(const AuxArgs<T>& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_gather_init<T>, dim3(a.ngather), dim3(64), 0, stream, a);
+}
+
+template <typename T>
+void launch_copy_out(const AuxArgs<T>& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_copy_out<T>, dim3(grid), dim3(256), 0, stream, a);
+}
+
+template <typename T>
+void launch_finalize(const AuxArgs<T>& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_finalize<T>, dim3((a.ngather + 63) / 64), dim3(64), 0, stream, a);
+}
+
+template <typename T>
+void launch_decompose(const AuxArgs<T>& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_decomp_sums<T>, dim3(grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_decomp_mass<T>, dim3(a.ngather), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(k_decomp_source<T>, dim3(grid), dim3(256), 0, stream, a);
+}
+
+template <typename T>
+void launch_adjoint(const AuxArgs<T>& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_adj_sums<T>, dim3(grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_adj_scalars<T>, dim3(a.ngather), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(k_adj_apply<T>, dim3(grid), dim3(256), 0, stream, a);
+}
+
+void launch_zero_counter(int32_t* counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
+}
+
+#define EMD_INST(T)                                                                  \
+    template void launch_copy_in<T>(const AuxArgs<T>&, int, int, hipStream_t);      \
+    template void launch_gather_init<T>(const AuxArgs<T>&, hipStream_t);            \
+    template void launch_copy_out<T>(const AuxArgs<T>&, int, hipStream_t);          \
+    template void launch_finalize<T>(const AuxArgs<T>&, hipStream_t);               \
+    template void launch_decompose<T>(const AuxArgs<T>&, int, hipStream_t);         \
+    template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);
+EMD_INST(float)
+EMD_INST(double)
+#undef EMD_INST
+
+}  // namespace emd

@@ -1,0 +1,150 @@
+// emd_internal.h -- device-side data structures and helpers of the MI355X EMD
+// library (not part of the public ABI).
+//
+// Solver state layout in HBM.  Every field of the solve (source s, flux components
+// u^x and u^t, potential phi, previous residual R) lives in the plan's workspace in
+// a padded copy of the batch: gather g occupies [poff, poff + nr * ld) with row
+// pitch ld = nt rounded up to a multiple of 4 elements, time contiguous, so that
+// each lane's 16-byte vector load is aligned.  u, phi and R are double-buffered:
+// sweep n reads buffer (n & 1) and writes buffer ((n & 1) ^ 1), so neighbouring
+// tiles that read halo rows never see a half-updated iterate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emd {
+
+// Per-gather status codes (same values as EMD_GATHER_* in the public header).
+enum : int {
+    ST_RUNNING = 0,
+    ST_CONVERGED = 1,
+    ST_MAX_ITER = 2,
+    ST_ZERO_SOURCE = 3,
+    ST_NONFINITE = 4,
+    ST_LS_FAIL = 5,
+    ST_MASS_IMBALANCE = 6
+};
+
+enum : int { LS_L2 = 0, LS_L1 = 1, LS_FIXED = 2, LS_REPLAY = 3 };
+enum : int { MASS_BALANCE = 0, MASS_UNIT = 1, MASS_NONE = 2 };
+
+// Number of partial sums a tile contributes to its gather per sweep:
+// <A,A>, <A,B>, <B,B>, <grad A,grad A>, <grad A,grad B>, <grad B,grad B>,
+// sum |u|, sum u^2 (A = div u_new + s, B = A - previous A).
+constexpr int NPART = 8;
+constexpr int WAVE = 64;
+// Lanes 0 and 63 of a sweep wave only carry the time-axis halo; lanes 1..62 own
+// output samples.
+constexpr int OUT_LANES = WAVE - 2;
+
+struct GatherMeta {
+    int32_t nr, nt, ld, ntiles;  // grid, padded pitch, sweep tiles of the gather
+    int32_t tile_base, pad0;     // first tile in the tile table
+    int64_t poff;                // element offset in the padded workspace fields
+    int64_t uoff;                // element offset in the caller's batch buffers
+    double dx, dt;               // EMD grid spacings
+    double cm;                   // cell measure (dx if nr > 1, times dt if nt > 1)
+    double alpha1;               // initial step (delta lambda)^(-1/2) or user's
+};
+
+struct Tile {
+    int32_t g, r0, c0, pad;      // gather, first output row, first output sample
+};
+
+// Per-gather scalar state, double-buffered by sweep parity.
+struct GState {
+    double alpha;      // alpha_k: step of the most recent primal update
+    double theta;      // theta_k
+    double snorm;      // ||s||_2
+    double alpha_max;  // cap on alpha
+    double rel_res;    // residual of the flux returned so far
+    double emd, transport;
+    int32_t iters;     // accepted iterations
+    int32_t status;
+    int32_t trials;    // backtracking steps so far
+    int32_t started;   // 0 until the first primal update has been applied
+    int32_t ubuf;      // buffer holding the returned u once status != RUNNING
+    int32_t phibuf;    // buffer holding the returned phi once status != RUNNING
+};
+
+struct SolveScalars {
+    double eps, xi, zeta, delta, tol_res;
+    int32_t max_iter, check_every, max_ls_trials, ls_mode;
+    const double* replay;  // LS_REPLAY: [ngather][ld_replay] accepted steps
+    int32_t ld_replay, pad;
+};
+
+// ---------------------------------------------------------------- reductions
+
+// Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the same
+// value: at each level lanes l and l^m add the same two operands (IEEE addition
+// is commutative), so the result is bitwise identical on all lanes and all waves
+// that reduce the same data.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+
+// Sum n records of NPART doubles (record p at src[p * NPART]) in a fixed order:
+// lane l adds records l, l + 64, ... in sequence, then the butterfly.
+__device__ __forceinline__ void reduce_records(const double* __restrict__ src, int n,
+                                               double out[NPART])
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    double acc[NPART];
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
+    for (int p = lane; p < n; p += WAVE) {
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) acc[q] += src[(int64_t)p * NPART + q];
+    }
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) out[q] = wave_sum(acc[q]);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).  Give
+// each XCD a contiguous range of logical blocks, so that tiles adjacent in the tile
+// table (neighbouring row strips of one gather) share that XCD's L2 for their halo
+// rows.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_logical_block()
+{
+    const int b = blockIdx.x;
+    const int per = gridDim.x >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; static constexpr int N = 4; };
+template <> struct Vec<double> { using type = double2; static constexpr int N = 2; };
+
+template <typename T>
+__device__ __forceinline__ void vload(const T* __restrict__ p, T (&x)[Vec<T>::N])
+{
+    using VT = typename Vec<T>::type;
+    VT v = *reinterpret_cast<const VT*>(p);
+    if constexpr (Vec<T>::N == 4) {
+        x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+        x[0] = v.x; x[1] = v.y;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void vstore(T* __restrict__ p, const T (&x)[Vec<T>::N])
+{
+    using VT = typename Vec<T>::type;
+    VT v;
+    if constexpr (Vec<T>::N == 4) {
+        v.x = x[0]; v.y = x[1]; v.z = x[2]; v.w = x[3];
+    } else {
+        v.x = x[0]; v.y = x[1];
+    }
+    *reinterpret_cast<VT*>(p) = v;
+}
+
+}  // namespace emd

@@ -1,0 +1,75 @@
+// emd_launch.h -- kernel argument blocks and launch wrappers shared by the host
+// code of the library and its kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "emd_internal.h"
+
+namespace emd {
+
+template <typename T>
+struct SweepArgs {
+    const GatherMeta* meta;
+    const Tile* tiles;
+    int32_t ntiles, rows;  // tiles in the table, receiver rows per tile
+    const T* s;            // padded source
+    T* ux[2];
+    T* ut[2];
+    T* phi[2];
+    T* R[2];
+    double* part[2];       // [tiles][NPART] partial sums, by sweep parity
+    GState* gst[2];        // [ngather], by sweep parity
+    int32_t* done;         // gathers that have finished
+    SolveScalars sc;
+};
+
+// Element-wise passes over the caller's batch layout and the padded workspace.
+template <typename T>
+struct AuxArgs {
+    const GatherMeta* meta;
+    const Tile* tiles;
+    int32_t ntiles, rows, ngather, mass_mode;
+    double mass_tol;
+    // caller's buffers (dense [nr][nt] at meta.uoff)
+    const T* pcal;
+    const T* pobs;
+    const T* s_user;
+    T* s_out;
+    T* f_out;
+    T* g_out;
+    const T* u_user_in;   // warm start [u^x | u^t] or NULL
+    const T* phi_user_in; // warm start or NULL
+    T* u_user_out;        // NULL: not returned
+    T* phi_user_out;
+    T* psi_out;
+    const T* phi_user;    // adjoint input
+    int64_t batch_len;
+    const double* mass;   // [ngather][3]
+    double* mass_out;     // [ngather][3]
+    const double* gbar;   // [ngather] or NULL
+    double* adj;          // [ngather][4] adjoint scalars
+    // workspace
+    T* s_pad;
+    T* ux[2];
+    T* ut[2];
+    T* phi[2];
+    T* R[2];
+    double* part;         // [tiles][NPART]
+    GState* gst;          // parity-0 state (initial / final)
+    int32_t* done;
+    double* emd_out;      // [ngather] or NULL
+    void* info_out;       // emd_solve_info[ngather] or NULL
+    double eps, delta_unused, alpha_max_factor;
+};
+
+template <typename T> void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream);
+template <typename T> void launch_copy_in(const AuxArgs<T>& a, int warm, int grid, hipStream_t stream);
+template <typename T> void launch_gather_init(const AuxArgs<T>& a, hipStream_t stream);
+template <typename T> void launch_copy_out(const AuxArgs<T>& a, int grid, hipStream_t stream);
+template <typename T> void launch_finalize(const AuxArgs<T>& a, hipStream_t stream);
+template <typename T> void launch_decompose(const AuxArgs<T>& a, int grid, hipStream_t stream);
+template <typename T> void launch_adjoint(const AuxArgs<T>& a, int grid, hipStream_t stream);
+void launch_zero_counter(int32_t* counter, hipStream_t stream);
+
+}  // namespace emd

@@ -1,0 +1,118 @@
+"""Host-side contract of the C ABI: the library loads, exports every function the
+public header declares, and rejects bad arguments before touching a device.
+No GPU is needed (no compute call is made)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1808_07284_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("library not built")
+    return L, L.load()
+
+
+def declared_functions():
+    names = []
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(emd_\w+)\s*\(", text, flags=re.M)
+    return names
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("emd_decompose", "emd_pdhg_solve", "emd_adjoint_source", "emd_plan_create"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    names = declared_functions()
+    assert set(names) == set(L.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_params_default_are_the_papers():
+    L, lib = _lib()
+    p = L.Params()
+    assert lib.emd_params_default(C.byref(p)) == 0
+    assert (p.eps, p.xi, p.zeta, p.delta) == (1e-4, 0.5, 0.99, 1e5)
+    assert p.ls_mode == L.LS_L2 and p.mass_mode == L.MASS_BALANCE and p.precision == L.F32
+    assert lib.emd_params_default(None) == 2
+
+
+def _create(L, lib, descs, batch_len, **over):
+    p = L.Params()
+    lib.emd_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    arr = (L.GatherDesc * max(len(descs), 1))()
+    for k, d in enumerate(descs):
+        arr[k] = L.GatherDesc(*d)
+    h = C.c_void_p()
+    st = lib.emd_plan_create(arr, len(descs), batch_len, C.byref(p), C.byref(h))
+    if st == 0:
+        lib.emd_plan_destroy(h)
+    return st, lib.emd_last_error().decode()
+
+
+@pytest.mark.parametrize("descs,batch,over,code", [
+    ([], 10, {}, 1),                                        # no gathers
+    ([(0, 5, 1.0, 1.0, 0)], 10, {}, 1),                     # nr = 0
+    ([(2, 5, 0.0, 1.0, 0)], 10, {}, 1),                     # dx = 0
+    ([(2, 5, 1.0, float("nan"), 0)], 10, {}, 1),            # dt NaN
+    ([(2, 5, 1.0, 1.0, 1)], 10, {}, 1),                     # past the batch end
+    ([(2, 5, 1.0, 1.0, 0), (1, 5, 1.0, 1.0, 8)], 20, {}, 1),  # overlapping gathers
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"xi": 1.0}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"zeta": 0.0}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"delta": -1.0}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"max_iter": 0}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"check_every": 0}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"precision": 7}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"mass_mode": 3}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 1}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 1}, 6),         # l1 test: not on the GPU
+])
+def test_plan_create_rejects_bad_arguments(descs, batch, over, code):
+    L, lib = _lib()
+    st, msg = _create(L, lib, descs, batch, **over)
+    assert st == code, msg
+    assert msg
+
+
+def test_plan_create_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L, lib = _lib()
+    st, msg = _create(L, lib, [(2, 5, 1.0, 1.0, 0)], 10)
+    assert st == 3, msg
+
+
+def test_null_pointers_are_rejected():
+    L, lib = _lib()
+    assert lib.emd_decompose(None, None, None, None, None, None, None, None) == 2
+    assert lib.emd_pdhg_solve(None, None, None, None, 0, None, None, None, None) == 2
+    assert lib.emd_adjoint_source(None, None, None, None, None, None, None, None) == 2
+    assert lib.emd_plan_destroy(None) == 0
+    assert lib.emd_status_string(1) == b"EMD_ERR_INVALID_ARGUMENT"
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1808_07284_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "emd_oracle" not in text and "liboracle" not in text, fn
