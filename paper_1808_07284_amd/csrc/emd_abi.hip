@@ -38,7 +38,7 @@ emd_status fail(emd_status st, const std::string& msg)
     } while (0)
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kDefaultRows = 32;
+constexpr int kDefaultRows = 16;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -128,8 +128,9 @@ void destroy_graph(emd_plan* plan)
 }
 
 // Tile table: per gather, time tiles of 62 * vec samples by row strips of `rows`,
-// ordered (gather, time tile, strip) so that strips sharing halo rows are
-// neighbours in the table (and therefore on the same XCD).
+// ordered (gather, strip, time tile): the four waves of a block are neighbours in
+// time, so the cache lines their windows share are read by one CU at once, and
+// consecutive blocks stay on one XCD (see the kernel's block mapping).
 emd_status build_tiles(emd_plan* plan)
 {
     const int span = OUT_LANES * plan->vec;
@@ -156,8 +157,8 @@ emd_status build_tiles(emd_plan* plan)
         m.pad0 = 0;
         const int ntt = (d.nt + span - 1) / span;
         const int nst = (d.nr + plan->rows - 1) / plan->rows;
-        for (int tt = 0; tt < ntt; ++tt)
-            for (int st = 0; st < nst; ++st) tiles.push_back(Tile{g, st * plan->rows, tt * span, 0});
+        for (int st = 0; st < nst; ++st)
+            for (int tt = 0; tt < ntt; ++tt) tiles.push_back(Tile{g, st * plan->rows, tt * span, 0});
         m.ntiles = (int32_t)tiles.size() - m.tile_base;
         poff += round_up((int64_t)d.nr * m.ld, 64);
     }
@@ -402,6 +403,12 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
         }
         if (!(d.dx > 0.0) || !(d.dt > 0.0) || !std::isfinite(d.dx) || !std::isfinite(d.dt)) {
             std::snprintf(msg, sizeof msg, "gather %d: dx and dt must be finite and > 0", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        // the sweep addresses a gather's padded field region with 32-bit byte offsets
+        const int64_t region = (int64_t)d.nr * ((d.nt + 3) / 4 * 4) * (p->precision == EMD_F64 ? 8 : 4);
+        if (region > ((int64_t)1 << 30)) {
+            std::snprintf(msg, sizeof msg, "gather %d: nr * nt too large (at most 1 GiB per field)", g);
             return fail(EMD_ERR_INVALID_ARGUMENT, msg);
         }
         if (d.offset < 0 || d.offset + (int64_t)d.nr * d.nt > batch_len) {

@@ -150,223 +150,386 @@ __device__ __forceinline__ T shrink_scaled(T v, T a, T inv)
     return m >= T(0) ? copysign(m, v) * inv : T(0);
 }
 
-template <typename T, bool PROX>
-__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const GatherMeta& gm,
-                           const Decision& d, int p)
+template <typename T>
+__device__ __forceinline__ void zero(T (&x)[Vec<T>::N])
+{
+#pragma unroll
+    for (int k = 0; k < Vec<T>::N; ++k) x[k] = T(0);
+}
+
+// Per-tile constants.  Field accesses go through raw buffer instructions on a
+// descriptor spanning the gather's padded region of that field: a lane or row that
+// must not touch memory gets an offset beyond the region, for which the hardware
+// returns zeros (loads) or drops the access (stores).  So every load and store is
+// issued unconditionally and the compiler can count them exactly in s_waitcnt.
+template <typename T>
+struct TileCtx {
+    static constexpr int V = Vec<T>::N;
+    int nr, ld, r0, rend, ibeg, ilast;
+    bool lane_out;
+    bool inb[V], jgt0[V], jlt[V];
+    T idx, idt, beta, theta, alpha, inv;
+    uint32_t row_bytes;            // ld * sizeof(T)
+    uint32_t vb_ld, vb_st;         // lane byte offsets for loads / stores (or OOB)
+    __amdgpu_buffer_rsrc_t uxi, uti, phi_i, ri, si, uxo, uto, phio, ro;
+};
+
+// Byte offset that is out of range of every gather region (regions are at most
+// 1 GiB, row offsets at most 1 GiB + 3 rows), without 32-bit wrap-around.
+constexpr uint32_t OOB = 0x40000000u;
+
+template <typename T>
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, uint32_t off, T (&x)[Vec<T>::N])
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    if constexpr (Vec<T>::N == 4) {
+        x[0] = __uint_as_float(v[0]);
+        x[1] = __uint_as_float(v[1]);
+        x[2] = __uint_as_float(v[2]);
+        x[3] = __uint_as_float(v[3]);
+    } else {
+        x[0] = __hiloint2double((int)v[1], (int)v[0]);
+        x[1] = __hiloint2double((int)v[3], (int)v[2]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, const T (&x)[Vec<T>::N])
+{
+    using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0u, 0, 0));
+    U4 v;
+    if constexpr (Vec<T>::N == 4) {
+        v[0] = __float_as_uint(x[0]);
+        v[1] = __float_as_uint(x[1]);
+        v[2] = __float_as_uint(x[2]);
+        v[3] = __float_as_uint(x[3]);
+    } else {
+        v[0] = (uint32_t)__double2loint(x[0]);
+        v[1] = (uint32_t)__double2hiint(x[0]);
+        v[2] = (uint32_t)__double2loint(x[1]);
+        v[3] = (uint32_t)__double2hiint(x[1]);
+    }
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Divergence of a flux on one row plus a source term:
+//   ([has_next] wxf - [has_prev] wx) / dx + ([j + 1 < nt] wt_{j+1} - [j > 0] wt_j) / dt + add,
+// the forward difference of the paper in the interior and minus the transpose of
+// the backward-difference gradient on the last row/column.
+template <typename T, bool EDGE>
+__device__ __forceinline__ void div_row(const TileCtx<T>& c, bool has_next, bool has_prev,
+                                        const T (&wx)[Vec<T>::N], const T (&wxf)[Vec<T>::N],
+                                        const T (&wt)[Vec<T>::N], T wt_next,
+                                        const T (&add)[Vec<T>::N], T (&out)[Vec<T>::N])
 {
     constexpr int V = Vec<T>::N;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int q = p ^ 1;
-    const int nr = gm.nr, nt = gm.nt, ld = gm.ld;
-    const T idx = T(1.0 / gm.dx), idt = T(1.0 / gm.dt);
-    const int r0 = tl.r0, c0 = tl.c0;
-    const int rend = min(r0 + a.rows, nr);
-    const int ibeg = max(r0 - 2, 0);
-    const int ilast = min(r0 + a.rows, nr);  // == nr: a virtual row closes the last strip
-    const int j0 = c0 - V + V * lane;
-    const bool lane_load = (j0 >= 0) && (j0 < nt);
-    const bool lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
-    bool inb[V], jgt0[V], jlt[V];
+    // the row conditions are uniform: fold them into the difference weights
+    const T wf = has_next ? c.idx : T(0), wb = has_prev ? c.idx : T(0);
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        const int j = j0 + k;
-        inb[k] = (j >= 0) && (j < nt);
-        jgt0[k] = j > 0;
-        jlt[k] = j + 1 < nt;
+        T ft = (k + 1 < V) ? wt[(k + 1) % V] : wt_next;
+        T bt = wt[k];
+        if constexpr (EDGE) {
+            ft = c.jlt[k] ? ft : T(0);
+            bt = c.jgt0[k] ? bt : T(0);
+        }
+        out[k] = fma(ft - bt, c.idt, fma(wxf[k], wf, fma(-wx[k], wb, add[k])));
     }
-    const T beta = T(d.beta), theta = T(d.theta), alpha = T(d.alpha);
-    const T inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+}
 
-    const int64_t base = gm.poff + j0;
-    const T* __restrict__ uxi = a.ux[p] + base;
-    const T* __restrict__ uti = a.ut[p] + base;
-    const T* __restrict__ phi_i = a.phi[p] + base;
-    const T* __restrict__ ri = a.R[p] + base;
-    const T* __restrict__ si = a.s + base;
-    T* __restrict__ uxo = a.ux[q] + base;
-    T* __restrict__ uto = a.ut[q] + base;
-    T* __restrict__ phio = a.phi[q] + base;
-    T* __restrict__ ro = a.R[q] + base;
-
-    T uxc[V], utc[V];
-    if (lane_load) {
-        vload(uxi + (int64_t)ibeg * ld, uxc);
-        vload(uti + (int64_t)ibeg * ld, utc);
-    } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) uxc[k] = utc[k] = T(0);
-    }
-    T phn_p[V], u1x_p[V], u1t_p[V], A_p[V], s_p[V], A1_pp[V], B1_pp[V];
-#pragma unroll
-    for (int k = 0; k < V; ++k)
-        phn_p[k] = u1x_p[k] = u1t_p[k] = A_p[k] = s_p[k] = A1_pp[k] = B1_pp[k] = T(0);
+// The row pipeline of one wavefront.  Every per-row quantity lives in register
+// sets indexed by the row's position relative to the first row (mod 4 for u^x,
+// mod 2 for everything else), and the loop is unrolled by four, so no register is
+// ever copied and each load writes registers whose previous row is already dead:
+//   u^x of row i + 3 is issued at the top of step i (two steps of latency hidden),
+//   u^t, phi, s, R of row i + 1 at the top of step i.
+// With B_{n+1} = div(u_{n+1} - u_n) and A_{n+1} = A_n + B_{n+1} the residual of the
+// new flux on row i - 1 needs only the flux change of rows i - 1 and i and A_n of
+// row i - 1 (B is formed from the small flux change instead of as a difference of
+// two nearly equal residuals).
+template <typename T, bool EDGE>
+struct Pipe {
+    static constexpr int V = Vec<T>::N;
+    const TileCtx<T>& c;
+    T UX[4][V];                              // u^x_n
+    T UT[2][V], PH[2][V], SV[2][V], RV[2][V];  // u^t_n, phi_{n-1}, s, R
+    T PHN[2][V], AN[2][V];   // phi_n and A_n = div u_n + s
+    T DX[2][V], DT[2][V];    // u_{n+1} - u_n
+    T A1[2][V], B1[2][V];    // A_{n+1}, B_{n+1} (one row behind)
     double acc[NPART];
-#pragma unroll
-    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
 
-    for (int i = ibeg; i <= ilast; ++i) {
-        const bool real = i < nr;
-        const int64_t ro_i = (int64_t)i * ld;
-        T uxn[V], utn[V], ph[V], sv[V], rv[V];
-        if (i + 1 < nr && lane_load) {
-            vload(uxi + ro_i + ld, uxn);
-            vload(uti + ro_i + ld, utn);
-        } else {
+    __device__ explicit Pipe(const TileCtx<T>& ctx) : c(ctx)
+    {
 #pragma unroll
-            for (int k = 0; k < V; ++k) uxn[k] = utn[k] = T(0);
+        for (int b = 0; b < 2; ++b) {
+            zero(PHN[b]); zero(AN[b]); zero(DX[b]); zero(DT[b]); zero(A1[b]); zero(B1[b]);
         }
-        if (real && lane_load) {
-            vload(phi_i + ro_i, ph);
-            vload(si + ro_i, sv);
-            vload(ri + ro_i, rv);
-        } else {
 #pragma unroll
-            for (int k = 0; k < V; ++k) ph[k] = sv[k] = rv[k] = T(0);
-        }
-        const bool own_row = (i >= r0) && (i < rend);
-        T phn[V], A[V], u1x[V], u1t[V];
-        if (real) {
-            // (1) residual of the current flux: A = div u_n + s
-            const T ut_next = __shfl_down(utc[0], 1, WAVE);
+        for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    }
+
+    // byte offset of row i for loads (rows past the grid fall out of range)
+    __device__ __forceinline__ uint32_t lrow(int i) const { return c.vb_ld + (uint32_t)i * c.row_bytes; }
+
+    __device__ __forceinline__ void load_x(int i, T (&ux)[V]) { bload(c.uxi, lrow(i), ux); }
+    __device__ __forceinline__ void load_rest(int i, T (&ut)[V], T (&ph)[V], T (&sv)[V], T (&rv)[V])
+    {
+        const uint32_t o = lrow(i);
+        bload(c.uti, o, ut);
+        bload(c.phi_i, o, ph);
+        bload(c.si, o, sv);
+        bload(c.ri, o, rv);
+    }
+
+    __device__ __forceinline__ void start()
+    {
+        load_x(c.ibeg, UX[0]);
+        load_x(c.ibeg + 1, UX[1]);
+        load_x(c.ibeg + 2, UX[2]);
+        load_rest(c.ibeg, UT[0], PH[0], SV[0], RV[0]);
+    }
+
+    // residual of the new flux on row im and its contribution to the products;
+    // DXf: flux change of row im + 1 (zeros past the grid), P: set of row im
+    template <int P>
+    __device__ __forceinline__ void close_row(int im, const T (&DXf)[V], bool has_next)
+    {
+        constexpr int Q = P ^ 1;
+        T b[V];
+        const T dt_next = __shfl_down(DT[P][0], 1, WAVE);
+        T zero_add[V];
+        zero(zero_add);
+        div_row<T, EDGE>(c, has_next, im > 0, DX[P], DXf, DT[P], dt_next, zero_add, b);
+        T a[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[k] = AN[P][k] + b[k];
+        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
+        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        if (im >= c.r0 && im < c.rend && c.lane_out) {
+            const bool xg = im > 0;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const T fx = (i + 1 < nr) ? uxn[k] : T(0);
-                const T bx = (i > 0) ? uxc[k] : T(0);
-                const T ftv = (k + 1 < V) ? utc[(k + 1) % V] : ut_next;
-                const T ft = jlt[k] ? ftv : T(0);
-                const T bt = jgt0[k] ? utc[k] : T(0);
-                A[k] = (fx - bx) * idx + (ft - bt) * idt + sv[k];
-            }
-            // (2) dual step: phi_n = phi_{n-1} + beta (A + theta (A - R))
-#pragma unroll
-            for (int k = 0; k < V; ++k) phn[k] = ph[k] + beta * (A[k] + theta * (A[k] - rv[k]));
-            if (own_row && lane_out) {
-                T w[V];
-#pragma unroll
-                for (int k = 0; k < V; ++k) w[k] = inb[k] ? phn[k] : T(0);
-                vstore(phio + ro_i, w);
-                if constexpr (PROX) {
-#pragma unroll
-                    for (int k = 0; k < V; ++k) w[k] = inb[k] ? A[k] : T(0);
-                    vstore(ro + ro_i, w);
+                if (EDGE && !c.inb[k]) continue;
+                const T ap = (k > 0) ? a[(k + V - 1) % V] : a_prev;
+                const T bp = (k > 0) ? b[(k + V - 1) % V] : b_prev;
+                const double gax = xg ? double((a[k] - A1[Q][k]) * c.idx) : 0.0;
+                const double gbx = xg ? double((b[k] - B1[Q][k]) * c.idx) : 0.0;
+                double gat = double((a[k] - ap) * c.idt);
+                double gbt = double((b[k] - bp) * c.idt);
+                if constexpr (EDGE) {
+                    gat = c.jgt0[k] ? gat : 0.0;
+                    gbt = c.jgt0[k] ? gbt : 0.0;
                 }
-            }
-            if constexpr (PROX) {
-                // (3) primal update with the backward-difference gradient of phi_n
-                const T ph_prev = __shfl_up(phn[V - 1], 1, WAVE);
-                T l1 = T(0), l2 = T(0);
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const T gx = (i > 0) ? (phn[k] - phn_p[k]) * idx : T(0);
-                    const T pprev = (k > 0) ? phn[(k + V - 1) % V] : ph_prev;
-                    const T gt = jgt0[k] ? (phn[k] - pprev) * idt : T(0);
-                    u1x[k] = shrink_scaled(uxc[k] + alpha * gx, alpha, inv);
-                    u1t[k] = shrink_scaled(utc[k] + alpha * gt, alpha, inv);
-                    if (inb[k]) {
-                        l1 += fabs(u1x[k]) + fabs(u1t[k]);
-                        l2 += u1x[k] * u1x[k] + u1t[k] * u1t[k];
-                    }
-                }
-                if (own_row && lane_out) {
-                    T w[V];
-#pragma unroll
-                    for (int k = 0; k < V; ++k) w[k] = inb[k] ? u1x[k] : T(0);
-                    vstore(uxo + ro_i, w);
-#pragma unroll
-                    for (int k = 0; k < V; ++k) w[k] = inb[k] ? u1t[k] : T(0);
-                    vstore(uto + ro_i, w);
-                    acc[6] += double(l1);
-                    acc[7] += double(l2);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < V; ++k) phn[k] = A[k] = u1x[k] = u1t[k] = T(0);
-        }
-
-        if constexpr (PROX) {
-            if (i > ibeg) {
-                // (4) residual of the new flux on row i-1 and its gradient
-                const int im = i - 1;
-                const T u1t_next = __shfl_down(u1t_p[0], 1, WAVE);
-                T A1[V], B1[V];
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const T fx = real ? u1x[k] : T(0);
-                    const T bx = (im > 0) ? u1x_p[k] : T(0);
-                    const T ftv = (k + 1 < V) ? u1t_p[(k + 1) % V] : u1t_next;
-                    const T ft = jlt[k] ? ftv : T(0);
-                    const T bt = jgt0[k] ? u1t_p[k] : T(0);
-                    A1[k] = (fx - bx) * idx + (ft - bt) * idt + s_p[k];
-                    B1[k] = A1[k] - A_p[k];
-                }
-                const T A1_prev = __shfl_up(A1[V - 1], 1, WAVE);
-                const T B1_prev = __shfl_up(B1[V - 1], 1, WAVE);
-                if (im >= r0 && im < rend && lane_out) {
-#pragma unroll
-                    for (int k = 0; k < V; ++k) {
-                        const T ap = (k > 0) ? A1[(k + V - 1) % V] : A1_prev;
-                        const T bp = (k > 0) ? B1[(k + V - 1) % V] : B1_prev;
-                        const double gax = (im > 0) ? double((A1[k] - A1_pp[k]) * idx) : 0.0;
-                        const double gbx = (im > 0) ? double((B1[k] - B1_pp[k]) * idx) : 0.0;
-                        const double gat = jgt0[k] ? double((A1[k] - ap) * idt) : 0.0;
-                        const double gbt = jgt0[k] ? double((B1[k] - bp) * idt) : 0.0;
-                        const double av = double(A1[k]), bv = double(B1[k]);
-                        if (inb[k]) {
-                            acc[0] += av * av;
-                            acc[1] += av * bv;
-                            acc[2] += bv * bv;
-                            acc[3] += gax * gax + gat * gat;
-                            acc[4] += gax * gbx + gat * gbt;
-                            acc[5] += gbx * gbx + gbt * gbt;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    A1_pp[k] = A1[k];
-                    B1_pp[k] = B1[k];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                u1x_p[k] = u1x[k];
-                u1t_p[k] = u1t[k];
+                const double av = double(a[k]), bv = double(b[k]);
+                acc[0] = fma(av, av, acc[0]);
+                acc[1] = fma(av, bv, acc[1]);
+                acc[2] = fma(bv, bv, acc[2]);
+                acc[3] = fma(gax, gax, fma(gat, gat, acc[3]));
+                acc[4] = fma(gax, gbx, fma(gat, gbt, acc[4]));
+                acc[5] = fma(gbx, gbx, fma(gbt, gbt, acc[5]));
             }
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            phn_p[k] = phn[k];
-            A_p[k] = A[k];
-            s_p[k] = sv[k];
-            uxc[k] = uxn[k];
-            utc[k] = utn[k];
+            A1[P][k] = a[k];
+            B1[P][k] = b[k];
         }
     }
 
-    if constexpr (PROX) {
+    // step on grid row i (i < nr); S: position of row i mod 4
+    template <int S, bool PROX>
+    __device__ __forceinline__ void step(int i)
+    {
+        constexpr int P = S & 1, Q = P ^ 1;
+        constexpr int X0 = S, X1 = (S + 1) & 3, X3 = (S + 3) & 3;
+        const bool own_row = (i >= c.r0) && (i < c.rend);
+        // store offset: rows outside the strip and halo lanes fall out of range
+        const uint32_t so = c.vb_st + (own_row ? (uint32_t)i * c.row_bytes : OOB);
+        const bool has_prev = i > 0;
+        load_x(i + 3, UX[X3]);  // row i - 1's registers
+        load_rest(i + 1, UT[Q], PH[Q], SV[Q], RV[Q]);
+
+        // (1) residual of the current flux: A_n = div u_n + s on row i
+        div_row<T, EDGE>(c, i + 1 < c.nr, has_prev, UX[X0], UX[X1], UT[P],
+                         __shfl_down(UT[P][0], 1, WAVE), SV[P], AN[P]);
+        // (2) dual step: phi_n = phi_{n-1} + beta (A_n + theta (A_n - R))
 #pragma unroll
-        for (int m = 0; m < NPART; ++m) acc[m] = wave_sum(acc[m]);
+        for (int k = 0; k < V; ++k)
+            PHN[P][k] = fma(c.beta, fma(c.theta, AN[P][k] - RV[P][k], AN[P][k]), PH[P][k]);
+        {
+            T w[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? PHN[P][k] : T(0);
+            bstore(c.phio, so, w);
+            if constexpr (PROX) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? AN[P][k] : T(0);
+                bstore(c.ro, so, w);
+            }
+        }
+        if constexpr (PROX) {
+            // (3) primal update with the backward-difference gradient of phi_n
+            const T ph_prev = __shfl_up(PHN[P][V - 1], 1, WAVE);
+            const T wgx = has_prev ? c.idx : T(0);
+            T u1x[V], u1t[V];
+            T l1 = T(0), l2 = T(0);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const T gx = (PHN[P][k] - PHN[Q][k]) * wgx;
+                const T pprev = (k > 0) ? PHN[P][(k + V - 1) % V] : ph_prev;
+                T gt = (PHN[P][k] - pprev) * c.idt;
+                if constexpr (EDGE) gt = c.jgt0[k] ? gt : T(0);
+                u1x[k] = shrink_scaled(fma(c.alpha, gx, UX[X0][k]), c.alpha, c.inv);
+                u1t[k] = shrink_scaled(fma(c.alpha, gt, UT[P][k]), c.alpha, c.inv);
+                DX[P][k] = u1x[k] - UX[X0][k];
+                DT[P][k] = u1t[k] - UT[P][k];
+                if (!EDGE || c.inb[k]) {
+                    l1 += fabs(u1x[k]) + fabs(u1t[k]);
+                    l2 = fma(u1x[k], u1x[k], fma(u1t[k], u1t[k], l2));
+                }
+            }
+            {
+                T w[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? u1x[k] : T(0);
+                bstore(c.uxo, so, w);
+#pragma unroll
+                for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? u1t[k] : T(0);
+                bstore(c.uto, so, w);
+            }
+            if (own_row && c.lane_out) {
+                acc[6] += double(l1);
+                acc[7] += double(l2);
+            }
+            // (4) residual of the new flux on row i - 1
+            if (i > c.ibeg) close_row<Q>(i - 1, DX[P], true);
+        }
+    }
+
+    // the march over the tile's rows: grid rows [ibeg, iend) -- through ilast when
+    // it is a grid row (it closes the strip's last own row), else through nr - 1
+    // followed by the virtual row nr
+    template <bool PROX>
+    __device__ __forceinline__ void run()
+    {
+        const int iend = min(c.ilast + 1, c.nr);
+        int i = c.ibeg;
+        for (; i + 3 < iend; i += 4) {
+            step<0, PROX>(i);
+            step<1, PROX>(i + 1);
+            step<2, PROX>(i + 2);
+            step<3, PROX>(i + 3);
+        }
+        int last_set = 1;  // parity set of the last row stepped
+        if (i < iend) {
+            step<0, PROX>(i++);
+            last_set = 0;
+            if (i < iend) {
+                step<1, PROX>(i++);
+                last_set = 1;
+                if (i < iend) {
+                    step<2, PROX>(i++);
+                    last_set = 0;
+                }
+            }
+        }
+        if constexpr (PROX) {
+            if (c.ilast == c.nr) {
+                T zero_row[V];
+                zero(zero_row);
+                if (last_set == 0) close_row<0>(c.nr - 1, zero_row, false);
+                else close_row<1>(c.nr - 1, zero_row, false);
+            }
+        }
+    }
+};
+
+// One tile: set up the lane's view, put the first rows in flight, then take the
+// gather's decision (which reduces the previous sweep's partials) while they load.
+template <typename T, bool EDGE>
+__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const GatherMeta& gm, int p)
+{
+    constexpr int V = Vec<T>::N;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int q = p ^ 1;
+    TileCtx<T> c;
+    c.nr = gm.nr;
+    c.ld = gm.ld;
+    const int nt = gm.nt;
+    c.r0 = tl.r0;
+    c.rend = min(tl.r0 + a.rows, gm.nr);
+    c.ibeg = max(tl.r0 - 2, 0);
+    c.ilast = min(tl.r0 + a.rows, gm.nr);  // == nr: the virtual row closes the last strip
+    const int j0 = tl.c0 - V + V * lane;
+    const bool lane_load = (j0 >= 0) && (j0 < nt);
+    c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int j = j0 + k;
+        c.inb[k] = (j >= 0) && (j < nt);
+        c.jgt0[k] = j > 0;
+        c.jlt[k] = j + 1 < nt;
+    }
+    c.idx = T(1.0 / gm.dx);
+    c.idt = T(1.0 / gm.dt);
+    c.row_bytes = (uint32_t)(gm.ld * sizeof(T));
+    c.vb_ld = lane_load ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    c.vb_st = c.lane_out ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    const int bytes = (int)((int64_t)gm.nr * gm.ld * sizeof(T));
+    auto rs = [&](const T* f) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f + gm.poff), 0, bytes, 0x00020000);
+    };
+    c.uxi = rs(a.ux[p]);
+    c.uti = rs(a.ut[p]);
+    c.phi_i = rs(a.phi[p]);
+    c.ri = rs(a.R[p]);
+    c.si = rs(a.s);
+    c.uxo = rs(a.ux[q]);
+    c.uto = rs(a.ut[q]);
+    c.phio = rs(a.phi[q]);
+    c.ro = rs(a.R[q]);
+
+    Pipe<T, EDGE> P(c);
+    P.start();
+    const Decision d = decide(a, p, tl.g, gm, tid == gm.tile_base);
+    if (!d.run) return;
+    c.beta = T(d.beta);
+    c.theta = T(d.theta);
+    c.alpha = T(d.alpha);
+    c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    if (d.prox) {
+        P.template run<true>();
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) P.acc[m] = wave_sum(P.acc[m]);
         if (lane == 0) {
             double* __restrict__ dst = a.part[q] + (int64_t)tid * NPART;
 #pragma unroll
-            for (int m = 0; m < NPART; ++m) dst[m] = acc[m];
+            for (int m = 0; m < NPART; ++m) dst[m] = P.acc[m];
         }
+    } else {
+        P.template run<false>();
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
 {
+    constexpr int V = Vec<T>::N;
     const int tid = uniform(xcd_logical_block() * (blockDim.x / WAVE) + threadIdx.x / WAVE);
     if (tid >= a.ntiles) return;
     const Tile tl = a.tiles[tid];
     const int g = uniform(tl.g);
     const GatherMeta gm = a.meta[g];
-    const Decision d = decide(a, parity, g, gm, tid == gm.tile_base);
-    if (!d.run) return;
-    if (d.prox) sweep_tile<T, true>(a, tl, tid, gm, d, parity);
-    else sweep_tile<T, false>(a, tl, tid, gm, d, parity);
+    if (a.gst[parity][g].status != ST_RUNNING) {
+        // finished gather: only carry its state to the other parity
+        if (tid == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0)
+            a.gst[parity ^ 1][g] = a.gst[parity][g];
+        return;
+    }
+    // tiles whose lanes all sit strictly inside (0, nt - 1) need no time-boundary masks
+    const bool edge = (tl.c0 - V < 1) || (tl.c0 + (WAVE - 1) * V > gm.nt - 1);
+    if (edge) sweep_tile<T, true>(a, tl, tid, gm, parity);
+    else sweep_tile<T, false>(a, tl, tid, gm, parity);
 }
 
 template <typename T>
