@@ -127,7 +127,7 @@ void destroy_graph(emd_plan* plan)
     plan->graph_chunk = 0;
 }
 
-// Tile table: per gather, time tiles of 62 * vec samples by row strips of `rows`,
+// Tile table: per gather, time tiles of 56 * vec samples by row strips of `rows`,
 // ordered (gather, strip, time tile): the four waves of a block are neighbours in
 // time, so the cache lines their windows share are read by one CU at once, and
 // consecutive blocks stay on one XCD (see the kernel's block mapping).
@@ -142,7 +142,9 @@ emd_status build_tiles(emd_plan* plan)
         GatherMeta& m = meta[g];
         m.nr = d.nr;
         m.nt = d.nt;
-        m.ld = (int32_t)round_up(d.nt, 4);
+        // rows start on 128-byte lines, so each wave's 896-byte output window is
+        // exactly seven whole lines
+        m.ld = (int32_t)round_up(d.nt, 32);
         m.poff = poff;
         m.uoff = d.offset;
         m.dx = d.dx;
@@ -406,7 +408,7 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
             return fail(EMD_ERR_INVALID_ARGUMENT, msg);
         }
         // the sweep addresses a gather's padded field region with 32-bit byte offsets
-        const int64_t region = (int64_t)d.nr * ((d.nt + 3) / 4 * 4) * (p->precision == EMD_F64 ? 8 : 4);
+        const int64_t region = (int64_t)d.nr * ((d.nt + 31) / 32 * 32) * (p->precision == EMD_F64 ? 8 : 4);
         if (region > ((int64_t)1 << 30)) {
             std::snprintf(msg, sizeof msg, "gather %d: nr * nt too large (at most 1 GiB per field)", g);
             return fail(EMD_ERR_INVALID_ARGUMENT, msg);

@@ -4,7 +4,7 @@
 // and the adjoint source (Section 2.3).
 //
 // All passes use the sweep tile table: a wavefront covers `rows` receiver rows by
-// 62 * V time samples of one gather (lanes 1..62, V samples each), so per-gather
+// 56 * V time samples of one gather (lanes 1..56, V samples each), so per-gather
 // sums are built from per-tile partials reduced in a fixed order (deterministic).
 #include "emd_internal.h"
 #include "emd_launch.h"

@@ -4,8 +4,9 @@
 // Solver state layout in HBM.  Every field of the solve (source s, flux components
 // u^x and u^t, potential phi, previous residual R) lives in the plan's workspace in
 // a padded copy of the batch: gather g occupies [poff, poff + nr * ld) with row
-// pitch ld = nt rounded up to a multiple of 4 elements, time contiguous, so that
-// each lane's 16-byte vector load is aligned.  u, phi and R are double-buffered:
+// pitch ld = nt rounded up to a multiple of 32 elements, time contiguous, so that
+// every row starts on a 128-byte cache line and each lane's 16-byte vector is
+// aligned.  u, phi and R are double-buffered:
 // sweep n reads buffer (n & 1) and writes buffer ((n & 1) ^ 1), so neighbouring
 // tiles that read halo rows never see a half-updated iterate.
 #pragma once
@@ -34,9 +35,13 @@ enum : int { MASS_BALANCE = 0, MASS_UNIT = 1, MASS_NONE = 2 };
 // sum |u|, sum u^2 (A = div u_new + s, B = A - previous A).
 constexpr int NPART = 8;
 constexpr int WAVE = 64;
-// Lanes 0 and 63 of a sweep wave only carry the time-axis halo; lanes 1..62 own
-// output samples.
-constexpr int OUT_LANES = WAVE - 2;
+// A sweep wave owns OUT_LANES * V consecutive time samples in lanes 1..OUT_LANES;
+// lanes 0 and OUT_LANES + 1 carry the time-axis halo, the remaining lanes idle.
+// 56 lanes x 16 bytes = 896 bytes = 7 whole 128-byte cache lines, so the stores of
+// a row never leave a partially written line behind (a partial line costs a fill
+// read and a whole-line write-back).
+constexpr int OUT_LANES = 56;
+constexpr int HALO_LANE_R = OUT_LANES + 1;
 
 struct GatherMeta {
     int32_t nr, nt, ld, ntiles;  // grid, padded pitch, sweep tiles of the gather

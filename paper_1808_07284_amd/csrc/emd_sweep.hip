@@ -20,14 +20,14 @@
 // sum |u|, sum u^2 for the next decision.  One HBM pass per iteration: read u, phi,
 // s, R (the previous residual A_n), write u, phi, R -- 36 bytes per cell in FP32.
 //
-// Work decomposition: a wavefront owns a tile of `rows` receiver rows by 62 * V
+// Work decomposition: a wavefront owns a tile of `rows` receiver rows by 56 * V
 // time samples (V = 4 floats or 2 doubles per lane, one 16-byte vector per field).
 // Lanes run along time (coalesced), the wave marches down the rows keeping the
 // previous rows in registers.  The operators couple a cell to its neighbours at
 // distance <= 2 rows back and 1 row ahead, and 2 samples back / 1 ahead in time:
 // rows are recomputed for the halo (the march starts 2 rows early and ends 1 row
-// late), and lanes 0 and 63 carry the time halo (their own samples are loaded and
-// computed but never stored or reduced).
+// late), and lanes 0 and 57 carry the time halo (their own samples are loaded and
+// computed but never stored or reduced); lanes 58..63 neither load nor store.
 #include "emd_internal.h"
 #include "emd_launch.h"
 
@@ -461,7 +461,7 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const
     c.ibeg = max(tl.r0 - 2, 0);
     c.ilast = min(tl.r0 + a.rows, gm.nr);  // == nr: the virtual row closes the last strip
     const int j0 = tl.c0 - V + V * lane;
-    const bool lane_load = (j0 >= 0) && (j0 < nt);
+    const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
     c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -526,8 +526,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
             a.gst[parity ^ 1][g] = a.gst[parity][g];
         return;
     }
-    // tiles whose lanes all sit strictly inside (0, nt - 1) need no time-boundary masks
-    const bool edge = (tl.c0 - V < 1) || (tl.c0 + (WAVE - 1) * V > gm.nt - 1);
+    // tiles whose loaded lanes (0..OUT_LANES + 1) all sit strictly inside (0, nt - 1)
+    // need no time-boundary masks
+    const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
     if (edge) sweep_tile<T, true>(a, tl, tid, gm, parity);
     else sweep_tile<T, false>(a, tl, tid, gm, parity);
 }
