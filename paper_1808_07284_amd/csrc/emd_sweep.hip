@@ -157,6 +157,14 @@ __device__ __forceinline__ void zero(T (&x)[Vec<T>::N])
     for (int k = 0; k < Vec<T>::N; ++k) x[k] = T(0);
 }
 
+template <typename T>
+__device__ __forceinline__ void swap2(bool s, T& x, T& y)
+{
+    const T a = s ? y : x, b = s ? x : y;
+    x = a;
+    y = b;
+}
+
 // Per-tile constants.  Field accesses go through raw buffer instructions on a
 // descriptor spanning the gather's padded region of that field: a lane or row that
 // must not touch memory gets an offset beyond the region, for which the hardware
@@ -250,7 +258,7 @@ __device__ __forceinline__ void div_row(const TileCtx<T>& c, bool has_next, bool
 template <typename T, bool EDGE>
 struct Pipe {
     static constexpr int V = Vec<T>::N;
-    const TileCtx<T>& c;
+    TileCtx<T> c;
     T UX[4][V];                              // u^x_n
     T UT[2][V], PH[2][V], SV[2][V], RV[2][V];  // u^t_n, phi_{n-1}, s, R
     T PHN[2][V], AN[2][V];   // phi_n and A_n = div u_n + s
@@ -435,10 +443,20 @@ struct Pipe {
         }
         if constexpr (PROX) {
             if (c.ilast == c.nr) {
+                // bring the last row into set 0 by value (selecting between register
+                // sets by a runtime index would push them out to scratch memory)
+                const bool swap = last_set == 1;
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    swap2(swap, DX[0][k], DX[1][k]);
+                    swap2(swap, DT[0][k], DT[1][k]);
+                    swap2(swap, AN[0][k], AN[1][k]);
+                    swap2(swap, A1[0][k], A1[1][k]);
+                    swap2(swap, B1[0][k], B1[1][k]);
+                }
                 T zero_row[V];
                 zero(zero_row);
-                if (last_set == 0) close_row<0>(c.nr - 1, zero_row, false);
-                else close_row<1>(c.nr - 1, zero_row, false);
+                close_row<0>(c.nr - 1, zero_row, false);
             }
         }
     }
@@ -493,10 +511,10 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const
     P.start();
     const Decision d = decide(a, p, tl.g, gm, tid == gm.tile_base);
     if (!d.run) return;
-    c.beta = T(d.beta);
-    c.theta = T(d.theta);
-    c.alpha = T(d.alpha);
-    c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    P.c.beta = T(d.beta);
+    P.c.theta = T(d.theta);
+    P.c.alpha = T(d.alpha);
+    P.c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
     if (d.prox) {
         P.template run<true>();
 #pragma unroll
