@@ -54,7 +54,8 @@ struct emd_plan {
     int vec = 4;              // elements per lane vector
     int rows = kDefaultRows;  // receiver rows per tile
     int64_t padded_len = 0;
-    int32_t ntiles = 0;
+    int32_t ntiles = 0;       // entries of the tile table (including empty padding)
+    int32_t nslots = 0;       // real tiles = partial-sum slots
     int grid = 0;             // blocks per tile-table launch (multiple of 8)
     int64_t cells = 0;
 
@@ -127,16 +128,23 @@ void destroy_graph(emd_plan* plan)
     plan->graph_chunk = 0;
 }
 
-// Tile table: per gather, time tiles of 56 * vec samples by row strips of `rows`,
-// ordered (gather, strip, time tile): the four waves of a block are neighbours in
-// time, so the cache lines their windows share are read by one CU at once, and
-// consecutive blocks stay on one XCD (see the kernel's block mapping).
+// Tile table.  A gather is cut into row strips of `rows` receivers by time tiles of
+// 56 * vec samples; its tiles own a contiguous range of partial-sum slots
+// [tile_base, tile_base + ntiles).  The table order serves the caches: the batch's
+// strips (gather-major) are split into 8 contiguous runs of equal cell count, one
+// per XCD (block b runs on XCD b % 8 and the kernel maps it to logical block
+// (b % 8) * per + b / 8, see xcd_logical_block), and inside a run the tiles go
+// strip-major: strip k + 1 of a gather is dispatched about when strip k finishes,
+// so the halo rows they share are still in that XCD's L2.  The four waves of a
+// block are neighbours in time.  Runs are padded to equal length with empty tiles.
 emd_status build_tiles(emd_plan* plan)
 {
     const int span = OUT_LANES * plan->vec;
-    std::vector<Tile> tiles;
+    constexpr int kXcd = 8;
     std::vector<GatherMeta> meta(plan->ngather);
+    std::vector<int> ntt(plan->ngather), nst(plan->ngather);
     int64_t poff = 0;
+    int32_t slots = 0;
     for (int g = 0; g < plan->ngather; ++g) {
         const emd_gather_desc& d = plan->desc[g];
         GatherMeta& m = meta[g];
@@ -155,35 +163,79 @@ emd_status build_tiles(emd_plan* plan)
         if (d.nt > 1) lam += 4.0 / (d.dt * d.dt);
         m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
                                              : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
-        m.tile_base = (int32_t)tiles.size();
+        ntt[g] = (d.nt + span - 1) / span;
+        nst[g] = (d.nr + plan->rows - 1) / plan->rows;
+        m.tile_base = slots;
+        m.ntiles = ntt[g] * nst[g];
         m.pad0 = 0;
-        const int ntt = (d.nt + span - 1) / span;
-        const int nst = (d.nr + plan->rows - 1) / plan->rows;
-        for (int st = 0; st < nst; ++st)
-            for (int tt = 0; tt < ntt; ++tt) tiles.push_back(Tile{g, st * plan->rows, tt * span, 0});
-        m.ntiles = (int32_t)tiles.size() - m.tile_base;
+        slots += m.ntiles;
         poff += round_up((int64_t)d.nr * m.ld, 64);
     }
+    // strips in gather-major order, cut into kXcd runs of about equal cells
+    struct Strip { int g, st; int64_t cells; };
+    std::vector<Strip> strips;
+    int64_t total = 0;
+    for (int g = 0; g < plan->ngather; ++g)
+        for (int st = 0; st < nst[g]; ++st) {
+            const int64_t c = (int64_t)std::min(plan->rows, meta[g].nr - st * plan->rows) * meta[g].nt;
+            strips.push_back(Strip{g, st, c});
+            total += c;
+        }
+    std::vector<std::vector<Tile>> runs(kXcd);
+    size_t s0 = 0;
+    int64_t acc = 0;
+    for (int x = 0; x < kXcd; ++x) {
+        const int64_t goal = total * (x + 1) / kXcd;
+        size_t s1 = s0;
+        while (s1 < strips.size() && (x == kXcd - 1 || acc + strips[s1].cells / 2 < goal)) acc += strips[s1++].cells;
+        // strip-major order inside the run: the j-th strip of every gather segment
+        for (int j = 0;; ++j) {
+            bool any = false;
+            for (size_t s = s0; s < s1; ++s) {
+                const bool first = (s == s0) || (strips[s - 1].g != strips[s].g);
+                if (!first) continue;
+                size_t e = s;
+                while (e < s1 && strips[e].g == strips[s].g) ++e;
+                if ((size_t)j >= e - s) continue;
+                any = true;
+                const int g = strips[s].g, st = strips[s + j].st;
+                for (int tt = 0; tt < ntt[g]; ++tt)
+                    runs[x].push_back(Tile{g, st * plan->rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
+            }
+            if (!any) break;
+        }
+        s0 = s1;
+    }
+    size_t run_len = 0;
+    for (auto& r : runs) run_len = std::max(run_len, r.size());
+    run_len = (size_t)round_up((int64_t)std::max<size_t>(run_len, 1), kWavesPerBlock);
+    std::vector<Tile> tiles;
+    tiles.reserve(run_len * kXcd);
+    for (auto& r : runs) {
+        tiles.insert(tiles.end(), r.begin(), r.end());
+        tiles.resize((tiles.size() + run_len - 1) / run_len * run_len, Tile{-1, 0, 0, 0});
+        if (r.empty()) tiles.resize(tiles.size() + run_len, Tile{-1, 0, 0, 0});
+    }
     if (tiles.size() > (size_t)INT32_MAX / 8) return fail(EMD_ERR_INVALID_ARGUMENT, "too many tiles");
-    const bool realloc_tiles = (int32_t)tiles.size() != plan->ntiles || !plan->d_tiles;
+    const bool realloc_tiles = (int32_t)tiles.size() != plan->ntiles || slots != plan->nslots || !plan->d_tiles;
     plan->ntiles = (int32_t)tiles.size();
+    plan->nslots = slots;
     plan->padded_len = poff;
-    const int blocks = (plan->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    plan->grid = (int)round_up(blocks, 8);
+    plan->grid = (int)(tiles.size() / kWavesPerBlock);  // kXcd runs of whole blocks
     if (realloc_tiles) {
         if (plan->d_tiles) (void)hipFree(plan->d_tiles);
         if (plan->d_part) (void)hipFree(plan->d_part);
         plan->d_tiles = nullptr;
         plan->d_part = nullptr;
         if (hipMalloc(&plan->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
-            hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * tiles.size()) != hipSuccess)
+            hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * slots) != hipSuccess)
             return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate the tile table");
     }
     if (!plan->d_meta && hipMalloc(&plan->d_meta, sizeof(GatherMeta) * plan->ngather) != hipSuccess)
         return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate gather metadata");
     HIP_TRY(hipMemcpy(plan->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(plan->d_meta, meta.data(), sizeof(GatherMeta) * meta.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(plan->d_part, 0, sizeof(double) * NPART * 2 * tiles.size()));
+    HIP_TRY(hipMemset(plan->d_part, 0, sizeof(double) * NPART * 2 * slots));
     destroy_graph(plan);
     return EMD_SUCCESS;
 }
@@ -256,7 +308,7 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
         a.ut[b] = field<T>(plan, 3 + b);
         a.phi[b] = field<T>(plan, 5 + b);
         a.R[b] = field<T>(plan, 7 + b);
-        a.part[b] = plan->d_part + (int64_t)b * plan->ntiles * NPART;
+        a.part[b] = plan->d_part + (int64_t)b * plan->nslots * NPART;
         a.gst[b] = plan->d_gst + (int64_t)b * plan->ngather;
     }
     a.done = plan->d_done;
@@ -469,7 +521,7 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
         return fail(EMD_ERR_HIP, "workspace initialisation failed");
     }
     plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
-                            (int64_t)sizeof(double) * NPART * 2 * plan->ntiles +
+                            (int64_t)sizeof(double) * NPART * 2 * plan->nslots +
                             (int64_t)sizeof(Tile) * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
     *out = plan;
     return EMD_SUCCESS;

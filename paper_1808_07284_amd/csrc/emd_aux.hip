@@ -5,7 +5,8 @@
 //
 // All passes use the sweep tile table: a wavefront covers `rows` receiver rows by
 // 56 * V time samples of one gather (lanes 1..56, V samples each), so per-gather
-// sums are built from per-tile partials reduced in a fixed order (deterministic).
+// sums are built from per-tile partials (one slot per tile, contiguous per gather)
+// reduced in a fixed order (deterministic).
 #include "emd_internal.h"
 #include "emd_launch.h"
 
@@ -14,7 +15,7 @@ namespace emd {
 namespace {
 
 struct TileView {
-    int tid, g, r0, rend, j0, lane;
+    int tid, slot, g, r0, rend, j0, lane;
     bool active;  // this lane owns samples in the tile
 };
 
@@ -28,6 +29,9 @@ __device__ __forceinline__ TileView tile_view(const AuxArgs<T>& a, GatherMeta& g
     if (!ok) return v;
     const Tile tl = a.tiles[v.tid];
     v.g = uniform(tl.g);
+    ok = v.g >= 0;  // padding entries do nothing
+    if (!ok) return v;
+    v.slot = uniform(tl.slot);
     gm = a.meta[v.g];
     v.lane = threadIdx.x & (WAVE - 1);
     v.r0 = tl.r0;
@@ -37,7 +41,7 @@ __device__ __forceinline__ TileView tile_view(const AuxArgs<T>& a, GatherMeta& g
     return v;
 }
 
-__device__ __forceinline__ void write_record(double* part, int tid, const double (&acc)[NPART])
+__device__ __forceinline__ void write_record(double* part, int slot, const double (&acc)[NPART])
 {
     const int lane = threadIdx.x & (WAVE - 1);
     double r[NPART];
@@ -45,7 +49,7 @@ __device__ __forceinline__ void write_record(double* part, int tid, const double
     for (int m = 0; m < NPART; ++m) r[m] = wave_sum(acc[m]);
     if (lane == 0) {
 #pragma unroll
-        for (int m = 0; m < NPART; ++m) part[(int64_t)tid * NPART + m] = r[m];
+        for (int m = 0; m < NPART; ++m) part[(int64_t)slot * NPART + m] = r[m];
     }
 }
 
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(256) void k_copy_in(AuxArgs<T> a, int warm)
         vstore(a.phi[0] + pr, ph);
         vstore(a.R[0] + pr, z);
     }
-    write_record(a.part, tv.tid, acc);
+    write_record(a.part, tv.slot, acc);
 }
 
 // One wavefront per gather: ||s||, start status and the parity-0 scalar state.
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_decomp_sums(AuxArgs<T> a)
             }
         }
     }
-    write_record(a.part, tv.tid, acc);
+    write_record(a.part, tv.slot, acc);
 }
 
 template <typename T>
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(256) void k_adj_sums(AuxArgs<T> a)
             }
         }
     }
-    write_record(a.part, tv.tid, acc);
+    write_record(a.part, tv.slot, acc);
 }
 
 // adj[4 g + 0] = scale dx dt gbar; [1] = mean phi (balance) or pf (unit); [2] = pg

@@ -54,7 +54,9 @@ struct GatherMeta {
 };
 
 struct Tile {
-    int32_t g, r0, c0, pad;      // gather, first output row, first output sample
+    int32_t g;      // gather (-1: empty padding entry)
+    int32_t r0, c0; // first output row, first output sample
+    int32_t slot;   // partial-sum slot (a gather's slots are contiguous)
 };
 
 // Per-gather scalar state, double-buffered by sweep parity.
@@ -113,9 +115,8 @@ __device__ __forceinline__ void reduce_records(const double* __restrict__ src, i
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).  Give
-// each XCD a contiguous range of logical blocks, so that tiles adjacent in the tile
-// table (neighbouring row strips of one gather) share that XCD's L2 for their halo
-// rows.  gridDim.x is a multiple of 8.
+// each XCD a contiguous range of logical blocks (one run of the tile table), so that
+// tiles adjacent in the table share that XCD's L2.  gridDim.x is a multiple of 8.
 __device__ __forceinline__ int xcd_logical_block()
 {
     const int b = blockIdx.x;

@@ -465,7 +465,7 @@ struct Pipe {
 // One tile: set up the lane's view, put the first rows in flight, then take the
 // gather's decision (which reduces the previous sweep's partials) while they load.
 template <typename T, bool EDGE>
-__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const GatherMeta& gm, int p)
+__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p)
 {
     constexpr int V = Vec<T>::N;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -509,7 +509,7 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const
 
     Pipe<T, EDGE> P(c);
     P.start();
-    const Decision d = decide(a, p, tl.g, gm, tid == gm.tile_base);
+    const Decision d = decide(a, p, tl.g, gm, tl.slot == gm.tile_base);
     if (!d.run) return;
     P.c.beta = T(d.beta);
     P.c.theta = T(d.theta);
@@ -520,7 +520,7 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, int tid, const
 #pragma unroll
         for (int m = 0; m < NPART; ++m) P.acc[m] = wave_sum(P.acc[m]);
         if (lane == 0) {
-            double* __restrict__ dst = a.part[q] + (int64_t)tid * NPART;
+            double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
 #pragma unroll
             for (int m = 0; m < NPART; ++m) dst[m] = P.acc[m];
         }
@@ -537,18 +537,19 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     if (tid >= a.ntiles) return;
     const Tile tl = a.tiles[tid];
     const int g = uniform(tl.g);
+    if (g < 0) return;  // padding entry
     const GatherMeta gm = a.meta[g];
     if (a.gst[parity][g].status != ST_RUNNING) {
         // finished gather: only carry its state to the other parity
-        if (tid == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0)
+        if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0)
             a.gst[parity ^ 1][g] = a.gst[parity][g];
         return;
     }
     // tiles whose loaded lanes (0..OUT_LANES + 1) all sit strictly inside (0, nt - 1)
     // need no time-boundary masks
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
-    if (edge) sweep_tile<T, true>(a, tl, tid, gm, parity);
-    else sweep_tile<T, false>(a, tl, tid, gm, parity);
+    if (edge) sweep_tile<T, true>(a, tl, gm, parity);
+    else sweep_tile<T, false>(a, tl, gm, parity);
 }
 
 template <typename T>

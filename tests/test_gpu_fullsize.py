@@ -1,0 +1,223 @@
+"""GPU checks at the workloads' full sizes, in the benchmark's launch configuration
+(default tiling, FP32, stop rule).  The oracle cannot run these solves to
+convergence on the CPU, so it checks what it can compute one by one from the
+library's outputs -- the residual and EMD of the returned flux, the adjoint of the
+returned potential -- plus properties that hold at any size (exact symmetry), and
+the 1D closed form for the single-trace study."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import log, make_plan, unpack
+from synth import (config1_pairs, config2_gather, config3_batch, config4_batch, config5_batch,
+                   Gather)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1808_07284_amd as E  # noqa: E402
+
+
+def _solve_all(plan, pcal, pobs):
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    u = plan.empty(2)
+    emd, phi, u, info = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
+    psi = E.emd_adjoint_source(plan, phi, pcal, pobs, mass)
+    torch.cuda.synchronize()
+    return (emd.cpu().numpy(), phi.cpu().numpy(), u.cpu().numpy(), E.info_numpy(info),
+            mass.cpu().numpy(), psi.cpu().numpy())
+
+
+def _check_gather(g, ux, ut, phi, psi, mass, emd, info, tol):
+    """Recompute with the oracle's operators what the library reported."""
+    ux = ux.astype(np.float64)
+    ut = ut.astype(np.float64)
+    s, _, _, mo = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+    np.testing.assert_allclose(mass[:2], mo[:2], rtol=1e-6)
+    d = oracle.div(ux, ut, g.dx, g.dt)
+    assert abs(d.sum()) <= 1e-9 * np.abs(d).sum()           # flux conserves mass
+    res = np.linalg.norm(d + s) / np.linalg.norm(s)
+    assert res <= tol * 1.05                                 # stop rule, recomputed in FP64
+    assert info["rel_res"] == pytest.approx(res, rel=2e-3, abs=2e-7)
+    e, _ = oracle.emd_value(ux, ut, g.dx, g.dt)
+    assert emd == pytest.approx(e, rel=1e-5)                 # EMD of the returned flux
+    ref = oracle.adjoint(phi.astype(np.float64), g.pcal, g.pobs, mass, g.dx, g.dt)
+    np.testing.assert_allclose(psi, ref, rtol=0, atol=4e-6 * np.abs(ref).max())
+
+
+def test_benchmark_batch_to_the_stop_rule():
+    gs = config3_batch()
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=100000)
+    log(f"64-gather batch, {sum(g.cells for g in gs)} cells, to 1e-5")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+    assert np.all(info["status"] == E.GATHER_STATUS.index("CONVERGED"))
+    phis, psis = unpack(phi, desc), unpack(psi, desc)
+    us = unpack(u, desc, 2)
+    for k in (0, 17, 41, 63):
+        log(f"  gather {k} {gs[k].nr}x{gs[k].nt}: it={info[k]['iters']} emd={emd[k]:.8e}")
+        _check_gather(gs[k], us[k][0], us[k][1], phis[k], psis[k], mass[k], emd[k], info[k], 1e-5)
+    # exact symmetry at full size: swapping predicted and observed negates s exactly,
+    # and the iteration is odd in s with sign-symmetric rounding
+    emd2, _, _, info2, _, _ = _solve_all(plan, pobs, pcal)
+    np.testing.assert_array_equal(emd2, emd)
+    np.testing.assert_array_equal(info2["iters"], info["iters"])
+    plan.close()
+
+
+def test_single_gather_to_the_stop_rule():
+    g = config2_gather()
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=200000)
+    log("single 400x2000 gather to 1e-5")
+    plan, pcal, pobs, desc = make_plan([g], p)
+    emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+    assert info[0]["status"] == E.GATHER_STATUS.index("CONVERGED")
+    us = unpack(u, desc, 2)
+    _check_gather(g, us[0][0], us[0][1], unpack(phi, desc)[0], unpack(psi, desc)[0], mass[0],
+                  emd[0], info[0], 1e-5)
+    plan.close()
+
+
+def closed_form_1d(s, dt, eps=1e-4):
+    S = np.cumsum(np.asarray(s, np.float64).reshape(-1))[:-1]
+    return dt * dt * np.abs(S).sum() + 0.5 * eps * dt ** 3 * (S * S).sum()
+
+
+def test_shift_study_against_closed_form():
+    # 41 single traces, FP64 to a 1e-7 residual: in 1D the flux is fixed by the
+    # constraint, so the EMD must match the exact optimum
+    gs = config1_pairs()
+    p = E.SolverParams(precision=E.F64, tol_res=1e-7, max_iter=10000000, sweeps_per_sync=4096)
+    log("41 single traces, FP64, 1e-7")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+    ref = np.array([closed_form_1d(oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)[0], g.dt) for g in gs])
+    shifts = np.arange(-200, 201, 10)
+    nz = shifts != 0
+    err = np.abs(emd[nz] - ref[nz]) / ref[nz]
+    st = [E.GATHER_STATUS[v] for v in info["status"]]
+    for k in range(len(gs)):
+        log(f"  shift {shifts[k]:4d} ms: {st[k]} it={info['iters'][k]} res={info['rel_res'][k]:.2e} "
+            f"emd={emd[k]:.10e} exact={ref[k]:.10e}")
+    log(f"  iters {info['iters'][nz].min()}..{info['iters'].max()}, max rel err {err.max():.2e}, "
+        f"statuses {sorted(set(st))}")
+    assert st[int(np.flatnonzero(~nz)[0])] == "ZERO_SOURCE" and emd[~nz][0] == 0.0
+    assert all(st[k] == "CONVERGED" for k in np.flatnonzero(nz))
+    assert err.max() <= 1e-6
+    # the misfit has a single minimum at zero shift (Section 3.1) and a flat tail
+    # beyond the overlap (Section 4)
+    i0 = int(np.argmin(emd))
+    assert shifts[i0] == 0
+    # beyond the overlap the exact values agree to ten digits, below the solves'
+    # accuracy, so monotonicity is asked to within that accuracy
+    slack = 1e-6 * emd.max()
+    assert np.all(np.diff(emd[:i0 + 1]) < slack) and np.all(np.diff(emd[i0:]) > -slack)
+    assert abs(emd[0] - emd[2]) <= 2e-3 * emd[0]
+    plan.close()
+
+
+def _crop(g, r0, t0, nr=32, nt=128):
+    pc = g.pcal[r0:r0 + nr, t0:t0 + nt].astype(np.float64)
+    po = g.pobs[r0:r0 + nr, t0:t0 + nt].astype(np.float64)
+    return Gather(pc, po, dx=1.0 / (nr - 1), dt=1.0 / (nt - 1), label=f"crop{r0},{t0}")
+
+
+def test_autograd_batch_and_finite_differences():
+    # forward + backward through autograd on 32 gathers of 2000 x 300
+    gs = config4_batch()
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=100000)
+    log("32 gathers 2000x300 through autograd")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    x = pcal.clone().requires_grad_(True)
+    e = E.emd_misfit(x, pobs, plan)
+    w = torch.linspace(0.5, 1.5, len(gs), dtype=torch.float64, device=plan.device)
+    (e * w).sum().backward()
+    torch.cuda.synchronize()
+    grad = unpack(x.grad.cpu().numpy(), desc)
+    assert np.all(np.isfinite(x.grad.cpu().numpy()))
+    # the backward is the adjoint of the forward's potential, chained and scaled
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    _, phi, _, _ = E.emd_pdhg_solve(plan, s, mass=mass)
+    phis = unpack(phi.cpu().numpy(), desc)
+    mass_h = mass.cpu().numpy()
+    for k in (0, 31):
+        ref = oracle.adjoint(phis[k].astype(np.float64), gs[k].pcal, gs[k].pobs, mass_h[k],
+                             gs[k].dx, gs[k].dt, gbar=float(w[k]))
+        np.testing.assert_allclose(grad[k], ref, rtol=0, atol=4e-6 * np.abs(ref).max())
+    plan.close()
+
+    # FP64 central finite differences on 128 x 32 sub-gathers cropped around the
+    # strongest event, against the library's adjoint and the oracle's phi-based one
+    crops = []
+    for g in gs[:2]:
+        a = np.abs(g.pobs.astype(np.float64))
+        r, t = np.unravel_index(np.argmax(a), a.shape)
+        crops.append(_crop(g, min(max(r - 16, 0), g.nr - 32), min(max(t - 64, 0), g.nt - 128)))
+    p64 = E.SolverParams(precision=E.F64, tol_res=1e-9, max_iter=2000000, sweeps_per_sync=1024)
+    rng = np.random.default_rng(11)
+    for c in crops:
+        # the oracle's own solve fixes the direction: its adjoint on the cells where
+        # its flux flows plus a random part.  The EMD is convex in the source and the
+        # potential is one of its subgradients (it is unique only up to a constant on
+        # each connected part of the flow), so the adjoint's directional derivative
+        # must lie between the backward and the forward difference quotients; the
+        # step moves the EMD by 1e-3 of itself, far above the solves' 1e-9 accuracy
+        r, m = oracle.misfit(c.pcal, c.pobs, c.dx, c.dt,
+                             params=oracle.Params(tol_res=1e-9, max_iter=3000000))
+        psi_o = oracle.adjoint(r.phi, c.pcal, c.pobs, m, c.dx, c.dt).reshape(-1)
+        flow = (np.abs(r.ux) + np.abs(r.ut)).reshape(-1) > 1e-3 * max(np.abs(r.ux).max(), np.abs(r.ut).max())
+        d = (psi_o / np.linalg.norm(psi_o) + 0.5 * rng.normal(size=c.cells) / np.sqrt(c.cells)) * flow
+        ora = float(psi_o @ d)
+        h = 1e-3 * r.emd / abs(ora)
+
+        cplan, cp, co, cdesc = make_plan([c], p64)
+        s, mass = E.emd_decompose(cplan, cp, co)
+        emd0, phi, _, info = E.emd_pdhg_solve(cplan, s, mass=mass)
+        psi = E.emd_adjoint_source(cplan, phi, cp, co, mass)
+        torch.cuda.synchronize()
+        ad = float(psi.cpu().numpy() @ d)
+
+        def emd_at(pc):
+            t = torch.from_numpy(pc.reshape(-1)).cuda()
+            ss, mm = E.emd_decompose(cplan, t, co)
+            ee, _, _, ii = E.emd_pdhg_solve(cplan, ss, mass=mm)
+            torch.cuda.synchronize()
+            return float(ee.cpu()[0])
+
+        e0 = float(emd0.cpu()[0])
+        fwd = (emd_at(c.pcal.reshape(-1) + h * d) - e0) / h
+        bwd = (e0 - emd_at(c.pcal.reshape(-1) - h * d)) / h
+        log(f"  {c.label}: backward {bwd:.6e} adjoint {ad:.6e} forward {fwd:.6e} oracle {ora:.6e}")
+        tol = 2e-3 * abs(ad)
+        assert bwd - tol <= ad <= fwd + tol
+        assert fwd - bwd <= 0.05 * abs(ad)
+        assert ad == pytest.approx(ora, rel=2e-3)
+        cplan.close()
+
+
+def test_large_batch_fixed_budget():
+    # 16 gathers of 4000 x 1600 (102 M cells, 3.7 GB of solver state): a fixed
+    # budget, then the oracle's recomputation on sampled gathers
+    gs = config5_batch()
+    p = E.SolverParams(precision=E.F32, tol_res=0.0, max_iter=150, check_every=150)
+    log(f"16 gathers 4000x1600, {sum(g.cells for g in gs)} cells, 150 iterations")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+    assert np.all(info["iters"] == 150) and np.all(np.isfinite(emd)) and np.all(emd > 0)
+    us = unpack(u, desc, 2)
+    phis, psis = unpack(phi, desc), unpack(psi, desc)
+    for k in (0, 15):
+        g = gs[k]
+        ux, ut = (c.astype(np.float64) for c in us[k])
+        s, _, _, _ = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+        d = oracle.div(ux, ut, g.dx, g.dt)
+        res = np.linalg.norm(d + s) / np.linalg.norm(s)
+        assert info[k]["rel_res"] == pytest.approx(res, rel=2e-3)
+        e, _ = oracle.emd_value(ux, ut, g.dx, g.dt)
+        assert emd[k] == pytest.approx(e, rel=1e-5)
+        ref = oracle.adjoint(phis[k].astype(np.float64), g.pcal, g.pobs, mass[k], g.dx, g.dt)
+        np.testing.assert_allclose(psis[k], ref, rtol=0, atol=4e-6 * np.abs(ref).max())
+    plan.close()
