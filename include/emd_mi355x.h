@@ -129,6 +129,8 @@ typedef struct {
     int64_t last_sweeps;      /* sweep launches of the last emd_pdhg_solve     */
     int64_t last_cell_updates;/* sum over gathers of nr * nt * iterations      */
     double last_sweep_ms;     /* GPU time from the first to the last sweep     */
+    int64_t last_table_rebuilds; /* times the last solve narrowed the sweep's tile
+                                  * table to its running gathers                  */
 } emd_plan_stats;
 
 typedef struct emd_plan emd_plan;
@@ -140,8 +142,8 @@ emd_status emd_params_default(emd_params* p);
 
 /* Create a plan for `ngather` gathers described by the host array h_desc, in a
  * batch of `batch_len` elements, on the current device.  Validates every
- * descriptor and parameter, copies them, and allocates the workspace (about
- * 7 field copies of the padded batch plus per-tile scalars).  *out receives the
+ * descriptor and parameter, copies them, and allocates the workspace (9 field
+ * copies of the padded batch plus per-tile scalars).  *out receives the
  * plan; it is NULL on failure. */
 emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64_t batch_len,
                            const emd_params* p, emd_plan** out);

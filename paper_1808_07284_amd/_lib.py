@@ -54,7 +54,8 @@ class PlanStats(C.Structure):
     _fields_ = [("ngather", C.c_int32), ("tiles", C.c_int32), ("rows_per_tile", C.c_int32),
                 ("samples_per_tile", C.c_int32), ("batch_len", C.c_int64), ("cells", C.c_int64),
                 ("workspace_bytes", C.c_int64), ("last_sweeps", C.c_int64),
-                ("last_cell_updates", C.c_int64), ("last_sweep_ms", C.c_double)]
+                ("last_cell_updates", C.c_int64), ("last_sweep_ms", C.c_double),
+                ("last_table_rebuilds", C.c_int64)]
 
 
 _lib = None

@@ -59,9 +59,14 @@ struct emd_plan {
     int grid = 0;             // blocks per tile-table launch (multiple of 8)
     int64_t cells = 0;
 
+    // host copy of the tiling: per-gather metadata, time tiles and row strips
+    std::vector<GatherMeta> h_meta;
+    std::vector<int> h_ntt, h_nst;
+
     // device memory
     GatherMeta* d_meta = nullptr;
-    Tile* d_tiles = nullptr;
+    Tile* d_tiles = nullptr;      // every gather's tiles (auxiliary kernels, first chunk)
+    Tile* d_tiles_act = nullptr;  // the running gathers' tiles, rebuilt as gathers finish
     void* d_fields = nullptr;  // one allocation: s, ux[2], ut[2], phi[2], R[2]
     double* d_part = nullptr;  // [2][tiles][NPART]
     GState* d_gst = nullptr;   // [2][ngather]
@@ -78,6 +83,7 @@ struct emd_plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int64_t last_sweeps = 0;
     int64_t last_cell_updates = 0;
+    int64_t last_rebuilds = 0;
     bool timing_valid = false;
     std::vector<emd_gather_desc> host_meta_cache;
 };
@@ -137,50 +143,27 @@ void destroy_graph(emd_plan* plan)
 // strip-major: strip k + 1 of a gather is dispatched about when strip k finishes,
 // so the halo rows they share are still in that XCD's L2.  The four waves of a
 // block are neighbours in time.  Runs are padded to equal length with empty tiles.
-emd_status build_tiles(emd_plan* plan)
+// Lay out the tiles of the selected gathers (sel[g] != 0): their strips, gather-
+// major, are cut into kXcd runs of about equal cells, each run strip-major, padded
+// to a common length that is a multiple of the block size.
+std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& sel)
 {
-    const int span = OUT_LANES * plan->vec;
     constexpr int kXcd = 8;
-    std::vector<GatherMeta> meta(plan->ngather);
-    std::vector<int> ntt(plan->ngather), nst(plan->ngather);
-    int64_t poff = 0;
-    int32_t slots = 0;
-    for (int g = 0; g < plan->ngather; ++g) {
-        const emd_gather_desc& d = plan->desc[g];
-        GatherMeta& m = meta[g];
-        m.nr = d.nr;
-        m.nt = d.nt;
-        // rows start on 128-byte lines, so each wave's 896-byte output window is
-        // exactly seven whole lines
-        m.ld = (int32_t)round_up(d.nt, 32);
-        m.poff = poff;
-        m.uoff = d.offset;
-        m.dx = d.dx;
-        m.dt = d.dt;
-        m.cm = (d.nr > 1 ? d.dx : 1.0) * (d.nt > 1 ? d.dt : 1.0);
-        double lam = 0.0;
-        if (d.nr > 1) lam += 4.0 / (d.dx * d.dx);
-        if (d.nt > 1) lam += 4.0 / (d.dt * d.dt);
-        m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
-                                             : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
-        ntt[g] = (d.nt + span - 1) / span;
-        nst[g] = (d.nr + plan->rows - 1) / plan->rows;
-        m.tile_base = slots;
-        m.ntiles = ntt[g] * nst[g];
-        m.pad0 = 0;
-        slots += m.ntiles;
-        poff += round_up((int64_t)d.nr * m.ld, 64);
-    }
-    // strips in gather-major order, cut into kXcd runs of about equal cells
+    const int span = OUT_LANES * plan->vec;
+    const std::vector<GatherMeta>& meta = plan->h_meta;
+    const std::vector<int>& ntt = plan->h_ntt;
+    const std::vector<int>& nst = plan->h_nst;
     struct Strip { int g, st; int64_t cells; };
     std::vector<Strip> strips;
     int64_t total = 0;
-    for (int g = 0; g < plan->ngather; ++g)
+    for (int g = 0; g < plan->ngather; ++g) {
+        if (!sel[g]) continue;
         for (int st = 0; st < nst[g]; ++st) {
             const int64_t c = (int64_t)std::min(plan->rows, meta[g].nr - st * plan->rows) * meta[g].nt;
             strips.push_back(Strip{g, st, c});
             total += c;
         }
+    }
     std::vector<std::vector<Tile>> runs(kXcd);
     size_t s0 = 0;
     int64_t acc = 0;
@@ -213,9 +196,48 @@ emd_status build_tiles(emd_plan* plan)
     tiles.reserve(run_len * kXcd);
     for (auto& r : runs) {
         tiles.insert(tiles.end(), r.begin(), r.end());
-        tiles.resize((tiles.size() + run_len - 1) / run_len * run_len, Tile{-1, 0, 0, 0});
-        if (r.empty()) tiles.resize(tiles.size() + run_len, Tile{-1, 0, 0, 0});
+        tiles.resize(tiles.size() + (run_len - r.size()), Tile{-1, 0, 0, 0});
     }
+    return tiles;
+}
+
+emd_status build_tiles(emd_plan* plan)
+{
+    const int span = OUT_LANES * plan->vec;
+    std::vector<GatherMeta> meta(plan->ngather);
+    std::vector<int> ntt(plan->ngather), nst(plan->ngather);
+    int64_t poff = 0;
+    int32_t slots = 0;
+    for (int g = 0; g < plan->ngather; ++g) {
+        const emd_gather_desc& d = plan->desc[g];
+        GatherMeta& m = meta[g];
+        m.nr = d.nr;
+        m.nt = d.nt;
+        // rows start on 128-byte lines, so each wave's 896-byte output window is
+        // exactly seven whole lines
+        m.ld = (int32_t)round_up(d.nt, 32);
+        m.poff = poff;
+        m.uoff = d.offset;
+        m.dx = d.dx;
+        m.dt = d.dt;
+        m.cm = (d.nr > 1 ? d.dx : 1.0) * (d.nt > 1 ? d.dt : 1.0);
+        double lam = 0.0;
+        if (d.nr > 1) lam += 4.0 / (d.dx * d.dx);
+        if (d.nt > 1) lam += 4.0 / (d.dt * d.dt);
+        m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
+                                             : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
+        ntt[g] = (d.nt + span - 1) / span;
+        nst[g] = (d.nr + plan->rows - 1) / plan->rows;
+        m.tile_base = slots;
+        m.ntiles = ntt[g] * nst[g];
+        m.pad0 = 0;
+        slots += m.ntiles;
+        poff += round_up((int64_t)d.nr * m.ld, 64);
+    }
+    plan->h_meta = meta;
+    plan->h_ntt = ntt;
+    plan->h_nst = nst;
+    const std::vector<Tile> tiles = layout_tiles(plan, std::vector<char>(plan->ngather, 1));
     if (tiles.size() > (size_t)INT32_MAX / 8) return fail(EMD_ERR_INVALID_ARGUMENT, "too many tiles");
     const bool realloc_tiles = (int32_t)tiles.size() != plan->ntiles || slots != plan->nslots || !plan->d_tiles;
     plan->ntiles = (int32_t)tiles.size();
@@ -224,10 +246,13 @@ emd_status build_tiles(emd_plan* plan)
     plan->grid = (int)(tiles.size() / kWavesPerBlock);  // kXcd runs of whole blocks
     if (realloc_tiles) {
         if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+        if (plan->d_tiles_act) (void)hipFree(plan->d_tiles_act);
         if (plan->d_part) (void)hipFree(plan->d_part);
         plan->d_tiles = nullptr;
+        plan->d_tiles_act = nullptr;
         plan->d_part = nullptr;
         if (hipMalloc(&plan->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
+            hipMalloc(&plan->d_tiles_act, sizeof(Tile) * tiles.size()) != hipSuccess ||
             hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * slots) != hipSuccess)
             return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate the tile table");
     }
@@ -319,12 +344,13 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
 // Enqueue `count` (even) sweeps starting at parity 0.  Uses a captured graph of
 // sweeps_per_sync launches when count equals that chunk size.
 template <typename T>
-emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int count, hipStream_t stream)
+emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int grid, int count, hipStream_t stream)
 {
     const int chunk = plan->params.sweeps_per_sync;
     if (count == chunk) {
-        std::vector<unsigned char> key(sizeof(a));
+        std::vector<unsigned char> key(sizeof(a) + sizeof(grid));
         std::memcpy(key.data(), &a, sizeof(a));
+        std::memcpy(key.data() + sizeof(a), &grid, sizeof(grid));
         if (!plan->graph || plan->graph_chunk != chunk || plan->graph_key != key) {
             destroy_graph(plan);
             hipStream_t cs;
@@ -332,7 +358,7 @@ emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int count, hipS
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, plan->grid, cs);
+                for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, grid, cs);
                 e = hipStreamEndCapture(cs, &g);
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0);
@@ -349,7 +375,7 @@ emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int count, hipS
         HIP_TRY(hipGraphLaunch(plan->graph, stream));
         return EMD_SUCCESS;
     }
-    for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, plan->grid, stream);
+    for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, grid, stream);
     HIP_TRY(hipGetLastError());
     return EMD_SUCCESS;
 }
@@ -375,24 +401,67 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     HIP_TRY(hipGetLastError());
 
     const int ls_mode = replay ? LS_REPLAY : plan->params.ls_mode;
-    const SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
+    SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
+    int grid = plan->grid;
     const int chunk = plan->params.sweeps_per_sync;
     // a gather needs iters + 1 sweeps; the last one applies the final dual step
     const int64_t max_sweeps = round_up((int64_t)plan->params.max_iter + 2, 2);
     int64_t sweeps = 0;
+    // Finished gathers leave the sweep's tile table: once the running gathers hold at
+    // most 7/8 of the table's cells, the table is rebuilt from them alone and spread
+    // over the XCDs again.  Tiles keep their shape and partial-sum slots, so every
+    // decision, and hence every result, is bitwise the same as with the full table.
+    int64_t table_cells = plan->cells;
+    int32_t known_out = 0;  // finished gathers seen at the last status read
+    int64_t rebuilds = 0;
+    std::vector<GState> gs(plan->ngather);
+    std::vector<char> sel(plan->ngather);
     HIP_TRY(hipEventRecord(plan->ev0, stream));
     for (;;) {
         // the finished count before any sweep (gathers with nothing to solve)
         HIP_TRY(hipMemcpyAsync(plan->h_done, plan->d_done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        if (*plan->h_done >= plan->ngather || sweeps >= max_sweeps) break;
+        const int32_t done = *plan->h_done;
+        if (done >= plan->ngather || sweeps >= max_sweeps) break;
+        if (sweeps > 0 && done > known_out) {
+            // Every chunk has an even number of sweeps, so buffer 0 holds the newest
+            // state and buffer 1 the state one sweep older (before the first sweep
+            // buffer 1 still holds a previous solve's state).  A gather already
+            // finished in buffer 1 has had its final state carried into both, and
+            // stays correct after it stops being swept.
+            HIP_TRY(hipMemcpyAsync(gs.data(), plan->d_gst + plan->ngather, sizeof(GState) * plan->ngather,
+                                   hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            int64_t live = 0;
+            int32_t out = 0;
+            for (int g = 0; g < plan->ngather; ++g) {
+                sel[g] = gs[g].status == ST_RUNNING;
+                if (sel[g]) live += (int64_t)plan->desc[g].nr * plan->desc[g].nt;
+                else ++out;
+            }
+            known_out = out;
+            if (live > 0 && live * 8 <= table_cells * 7) {
+                const std::vector<Tile> tiles = layout_tiles(plan, sel);
+                if ((int64_t)tiles.size() <= plan->ntiles) {
+                    HIP_TRY(hipMemcpyAsync(plan->d_tiles_act, tiles.data(), sizeof(Tile) * tiles.size(),
+                                           hipMemcpyHostToDevice, stream));
+                    HIP_TRY(hipStreamSynchronize(stream));
+                    sa.tiles = plan->d_tiles_act;
+                    sa.ntiles = (int32_t)tiles.size();
+                    grid = (int)(tiles.size() / kWavesPerBlock);
+                    table_cells = live;
+                    ++rebuilds;
+                }
+            }
+        }
         const int count = (int)std::min<int64_t>(chunk, max_sweeps - sweeps);
-        emd_status st = enqueue_sweeps<T>(plan, sa, count, stream);
+        emd_status st = enqueue_sweeps<T>(plan, sa, grid, count, stream);
         if (st != EMD_SUCCESS) return st;
         sweeps += count;
     }
     HIP_TRY(hipEventRecord(plan->ev1, stream));
     plan->last_sweeps = sweeps;
+    plan->last_rebuilds = rebuilds;
     plan->timing_valid = true;
 
     a.gst = plan->d_gst;  // parity 0: every chunk has an even number of sweeps
@@ -522,7 +591,7 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
     }
     plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
                             (int64_t)sizeof(double) * NPART * 2 * plan->nslots +
-                            (int64_t)sizeof(Tile) * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
+                            (int64_t)sizeof(Tile) * 2 * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
     *out = plan;
     return EMD_SUCCESS;
 }
@@ -534,6 +603,7 @@ emd_status emd_plan_destroy(emd_plan* plan)
     destroy_graph(plan);
     if (plan->d_meta) (void)hipFree(plan->d_meta);
     if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    if (plan->d_tiles_act) (void)hipFree(plan->d_tiles_act);
     if (plan->d_fields) (void)hipFree(plan->d_fields);
     if (plan->d_part) (void)hipFree(plan->d_part);
     if (plan->d_gst) (void)hipFree(plan->d_gst);
@@ -588,6 +658,7 @@ emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out)
     out->last_sweeps = plan->last_sweeps;
     out->last_cell_updates = plan->last_cell_updates;
     out->last_sweep_ms = 0.0;
+    out->last_table_rebuilds = plan->last_rebuilds;
     if (plan->timing_valid) {
         float ms = 0.f;
         if (hipEventSynchronize(plan->ev1) == hipSuccess &&

@@ -116,3 +116,31 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "emd_oracle" not in text and "liboracle" not in text, fn
+
+
+def _header_structs():
+    text = open(os.path.join(ROOT, "include", "emd_mi355x.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef\s+struct\s*\{(.*?)\}\s*(emd_\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ctype, names = decl.split(None, 1)
+            fields += [(n.strip(), ctype) for n in names.split(",")]
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_mirror_the_header():
+    from paper_1808_07284_amd import _lib as L
+    ctypes_of = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double}
+    structs = _header_structs()
+    pairs = {"emd_gather_desc": L.GatherDesc, "emd_params": L.Params,
+             "emd_solve_info": L.SolveInfo, "emd_plan_stats": L.PlanStats}
+    assert set(pairs) <= set(structs)
+    for hname, cls in pairs.items():
+        assert [(n, ctypes_of[t]) for n, t in structs[hname]] == \
+            [(n, t) for n, t in cls._fields_], hname

@@ -291,6 +291,37 @@ def test_repeat_solves_are_bitwise_deterministic():
     plan.close()
 
 
+def test_narrowed_tile_table_gives_bitwise_identical_results():
+    # gathers that converge at different iterations plus one with nothing to solve;
+    # with a status read every two sweeps the sweep's tile table is narrowed to the
+    # running gathers several times, with one chunk of sweeps never
+    gs = ragged_batch(np.float32)
+    z = gs[1]
+    gs.append(type(z)(z.pcal.copy(), z.pcal.copy(), z.dx, z.dt, "zero source"))
+    res = {}
+    for spsync in (4096, 2):
+        p = E.SolverParams(precision=E.F32, max_iter=4000, tol_res=1e-4, sweeps_per_sync=spsync)
+        plan, pcal, pobs, desc = make_plan(gs, p)
+        res[spsync] = _solve(plan, pcal, pobs)
+        res[spsync, "rebuilds"] = plan.query()["last_table_rebuilds"]
+        if spsync == 2:
+            # a second solve on the same plan starts from stale state buffers
+            again = _solve(plan, pcal, pobs)
+            for k in range(3):
+                np.testing.assert_array_equal(again[k], res[2][k])
+            np.testing.assert_array_equal(again[3], res[2][3])
+        plan.close()
+    info = res[2][3]
+    log(f"  iterations {info['iters'].tolist()}, statuses {info['status'].tolist()}, "
+        f"rebuilds {res[4096, 'rebuilds']} / {res[2, 'rebuilds']}")
+    assert res[4096, "rebuilds"] == 0 and res[2, "rebuilds"] >= 1
+    assert len(set(info["iters"][info["status"] == 1].tolist())) >= 2
+    assert info["status"][-1] == E.GATHER_STATUS.index("ZERO_SOURCE")
+    for k in range(3):
+        np.testing.assert_array_equal(res[2][k], res[4096][k])
+    np.testing.assert_array_equal(res[2][3], res[4096][3])
+
+
 def test_autograd_backward_is_the_adjoint_source():
     gs = to_precision([random_small_pair(10, 64, 21), random_small_pair(6, 30, 22)], np.float32)
     p = E.SolverParams(precision=E.F32, max_iter=100, tol_res=0.0, check_every=100)
