@@ -140,12 +140,14 @@ void destroy_graph(emd_plan* plan)
 // strips (gather-major) are split into 8 contiguous runs of equal cell count, one
 // per XCD (block b runs on XCD b % 8 and the kernel maps it to logical block
 // (b % 8) * per + b / 8, see xcd_logical_block), and inside a run the tiles go
-// strip-major: strip k + 1 of a gather is dispatched about when strip k finishes,
-// so the halo rows they share are still in that XCD's L2.  The four waves of a
-// block are neighbours in time.  Runs are padded to equal length with empty tiles.
+// gather by gather, strip by strip: strips k and k + 1 of a gather start at about
+// the same time and march in opposite directions (the sweep's even strips go down,
+// odd strips up), so both read the rows they share at about the same moment and
+// the second read hits that XCD's L2.  The four waves of a block are neighbours in
+// time.  Runs are padded to equal length with empty tiles.
 // Lay out the tiles of the selected gathers (sel[g] != 0): their strips, gather-
-// major, are cut into kXcd runs of about equal cells, each run strip-major, padded
-// to a common length that is a multiple of the block size.
+// major, are cut into kXcd runs of about equal cells, padded to a common length
+// that is a multiple of the block size.
 std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& sel)
 {
     constexpr int kXcd = 8;
@@ -171,21 +173,12 @@ std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& se
         const int64_t goal = total * (x + 1) / kXcd;
         size_t s1 = s0;
         while (s1 < strips.size() && (x == kXcd - 1 || acc + strips[s1].cells / 2 < goal)) acc += strips[s1++].cells;
-        // strip-major order inside the run: the j-th strip of every gather segment
-        for (int j = 0;; ++j) {
-            bool any = false;
-            for (size_t s = s0; s < s1; ++s) {
-                const bool first = (s == s0) || (strips[s - 1].g != strips[s].g);
-                if (!first) continue;
-                size_t e = s;
-                while (e < s1 && strips[e].g == strips[s].g) ++e;
-                if ((size_t)j >= e - s) continue;
-                any = true;
-                const int g = strips[s].g, st = strips[s + j].st;
-                for (int tt = 0; tt < ntt[g]; ++tt)
-                    runs[x].push_back(Tile{g, st * plan->rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
-            }
-            if (!any) break;
+        // gather by gather, strip by strip: a strip's neighbours are dispatched right
+        // after it, while the rows they share are still in this XCD's L2
+        for (size_t s = s0; s < s1; ++s) {
+            const int g = strips[s].g, st = strips[s].st;
+            for (int tt = 0; tt < ntt[g]; ++tt)
+                runs[x].push_back(Tile{g, st * plan->rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
         }
         s0 = s1;
     }

@@ -22,12 +22,16 @@
 //
 // Work decomposition: a wavefront owns a tile of `rows` receiver rows by 56 * V
 // time samples (V = 4 floats or 2 doubles per lane, one 16-byte vector per field).
-// Lanes run along time (coalesced), the wave marches down the rows keeping the
-// previous rows in registers.  The operators couple a cell to its neighbours at
-// distance <= 2 rows back and 1 row ahead, and 2 samples back / 1 ahead in time:
-// rows are recomputed for the halo (the march starts 2 rows early and ends 1 row
-// late), and lanes 0 and 57 carry the time halo (their own samples are loaded and
-// computed but never stored or reduced); lanes 58..63 neither load nor store.
+// Lanes run along time (coalesced), the wave marches along the rows keeping the
+// neighbouring rows in registers: down on even strips, up on odd ones, so that two
+// tiles sharing halo rows read them at about the same time (see PipeUp).  The
+// operators couple a cell to its neighbours at distance <= 2 rows above and 1 row
+// below, and 2 samples back / 1 ahead in time: rows are recomputed for the halo
+// (2 rows above the tile and 1 below), and lanes 0 and 57 carry the time halo
+// (their own samples are loaded and computed but never stored or reduced); lanes
+// 58..63 neither load nor store.
+#include <type_traits>
+
 #include "emd_internal.h"
 #include "emd_launch.h"
 
@@ -279,10 +283,15 @@ struct Pipe {
     // byte offset of row i for loads (rows past the grid fall out of range)
     __device__ __forceinline__ uint32_t lrow(int i) const { return c.vb_ld + (uint32_t)i * c.row_bytes; }
 
-    __device__ __forceinline__ void load_x(int i, T (&ux)[V]) { bload(c.uxi, lrow(i), ux); }
+    // The prefetches run ahead of the march; rows the tile never reads (u^x past
+    // ilast + 1, the other fields past ilast) go out of range instead of to memory.
+    __device__ __forceinline__ void load_x(int i, T (&ux)[V])
+    {
+        bload(c.uxi, i <= c.ilast + 1 ? lrow(i) : OOB, ux);
+    }
     __device__ __forceinline__ void load_rest(int i, T (&ut)[V], T (&ph)[V], T (&sv)[V], T (&rv)[V])
     {
-        const uint32_t o = lrow(i);
+        const uint32_t o = i <= c.ilast ? lrow(i) : OOB;
         bload(c.uti, o, ut);
         bload(c.phi_i, o, ph);
         bload(c.si, o, sv);
@@ -462,9 +471,225 @@ struct Pipe {
     }
 };
 
+// The upward march, used on odd strips.  A tile shares its halo rows with the
+// strips above and below; if every tile marched down, the two reads of a shared
+// row would be a whole tile lifetime apart and the second would miss the L2.  With
+// even strips marching down and odd strips up, both tiles at every strip boundary
+// read the shared rows near the start of their march, or both near the end.
+// The per-cell arithmetic is that of the downward march, with the same operands in
+// the same order, so the fields are bitwise the same; only the order in which the
+// cells are summed into the partials differs.  Marching up, the flux update of
+// row i + 1 needs phi_n of the row above it, row i, so it runs one row behind the
+// dual step, and the residual of the new flux one row behind that:
+//   step i: A_n and phi_n of row i, u_{n+1} of row i + 1, residual of row i + 1.
+// The x-gradient of the new residual at row i + 1 pairs it with row i + 2, closed
+// one step earlier.  The march ends at a virtual row -1 when it reaches the top of
+// the grid, so that row 0 gets its flux update and residual (nothing is loaded or
+// stored for row -1, and its gradient weight is zero).
+template <typename T, bool EDGE>
+struct PipeUp {
+    static constexpr int V = Vec<T>::N;
+    TileCtx<T> c;
+    int ib;                                // bottom row of the march
+    T UX[4][V], UT[4][V];                  // u_n: row i in set S, i + 1 in S + 3
+    T PH[2][V], SV[2][V], RV[2][V];        // phi_{n-1}, s, R: row i (P), row i - 1 (Q)
+    T PHN[2][V], AN[2][V];                 // phi_n, A_n: row i (P), row i + 1 (Q)
+    T DX[2][V], DT[2][V];                  // u_{n+1} - u_n: row i + 1 (P), row i + 2 (Q)
+    T A1[V], B1[V];                        // A_{n+1}, B_{n+1} of the last residual row
+    double acc[NPART];
+
+    __device__ explicit PipeUp(const TileCtx<T>& ctx) : c(ctx)
+    {
+        ib = min(c.ilast, c.nr - 1);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            zero(PHN[b]); zero(AN[b]); zero(DX[b]); zero(DT[b]);
+        }
+        zero(A1);
+        zero(B1);
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    }
+
+    __device__ __forceinline__ uint32_t lrow(int i) const { return c.vb_ld + (uint32_t)i * c.row_bytes; }
+
+    // rows above the march's top row are never read: they go out of range
+    __device__ __forceinline__ void load_u(int i, T (&ux)[V], T (&ut)[V])
+    {
+        const uint32_t o = i >= c.ibeg ? lrow(i) : OOB;
+        bload(c.uxi, o, ux);
+        bload(c.uti, o, ut);
+    }
+    __device__ __forceinline__ void load_rest(int i, T (&ph)[V], T (&sv)[V], T (&rv)[V])
+    {
+        const uint32_t o = i >= c.ibeg ? lrow(i) : OOB;
+        bload(c.phi_i, o, ph);
+        bload(c.si, o, sv);
+        bload(c.ri, o, rv);
+    }
+
+    __device__ __forceinline__ void start()
+    {
+        load_u(ib, UX[0], UT[0]);
+        // u^x of the row below the march (zeros past the grid); u^t there is unused
+        bload(c.uxi, lrow(ib + 1), UX[3]);
+        zero(UT[3]);
+        load_u(ib - 1, UX[1], UT[1]);
+        load_rest(ib, PH[0], SV[0], RV[0]);
+    }
+
+    // residual of the new flux on row im: its products, and the x-gradient products
+    // of row im + 1 (whose residual is in A1, B1)
+    template <int P>
+    __device__ __forceinline__ void close_row(int im)
+    {
+        constexpr int Q = P ^ 1;
+        T b[V];
+        const T dt_next = __shfl_down(DT[P][0], 1, WAVE);
+        T zero_add[V];
+        zero(zero_add);
+        div_row<T, EDGE>(c, im + 1 < c.nr, im > 0, DX[P], DX[Q], DT[P], dt_next, zero_add, b);
+        T a[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[k] = AN[Q][k] + b[k];
+        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
+        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        const bool own = im >= c.r0 && im < c.rend;
+        const bool own_below = im + 1 >= c.r0 && im + 1 < c.rend;
+        if ((own || own_below) && c.lane_out) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (EDGE && !c.inb[k]) continue;
+                if (own) {
+                    const T ap = (k > 0) ? a[(k + V - 1) % V] : a_prev;
+                    const T bp = (k > 0) ? b[(k + V - 1) % V] : b_prev;
+                    double gat = double((a[k] - ap) * c.idt);
+                    double gbt = double((b[k] - bp) * c.idt);
+                    if constexpr (EDGE) {
+                        gat = c.jgt0[k] ? gat : 0.0;
+                        gbt = c.jgt0[k] ? gbt : 0.0;
+                    }
+                    const double av = double(a[k]), bv = double(b[k]);
+                    acc[0] = fma(av, av, acc[0]);
+                    acc[1] = fma(av, bv, acc[1]);
+                    acc[2] = fma(bv, bv, acc[2]);
+                    acc[3] = fma(gat, gat, acc[3]);
+                    acc[4] = fma(gat, gbt, acc[4]);
+                    acc[5] = fma(gbt, gbt, acc[5]);
+                }
+                if (own_below) {
+                    const double gax = double((A1[k] - a[k]) * c.idx);
+                    const double gbx = double((B1[k] - b[k]) * c.idx);
+                    acc[3] = fma(gax, gax, acc[3]);
+                    acc[4] = fma(gax, gbx, acc[4]);
+                    acc[5] = fma(gbx, gbx, acc[5]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            A1[k] = a[k];
+            B1[k] = b[k];
+        }
+    }
+
+    // step on row i (ibeg - 1 <= i <= ib); S = (ib - i) mod 4; HEAD: the first
+    // step, which has no row below it to update
+    template <int S, bool HEAD>
+    __device__ __forceinline__ void step(int i)
+    {
+        constexpr int P = S & 1, Q = P ^ 1;
+        constexpr int X0 = S, X2 = (S + 2) & 3, X3 = (S + 3) & 3;
+        const bool own_i = (i >= c.r0) && (i < c.rend);
+        const uint32_t so_i = c.vb_st + (own_i ? (uint32_t)i * c.row_bytes : OOB);
+        load_u(i - 2, UX[X2], UT[X2]);
+        load_rest(i - 1, PH[Q], SV[Q], RV[Q]);
+
+        // (1) residual of the current flux: A_n = div u_n + s on row i
+        div_row<T, EDGE>(c, i + 1 < c.nr, i > 0, UX[X0], UX[X3], UT[X0],
+                         __shfl_down(UT[X0][0], 1, WAVE), SV[P], AN[P]);
+        // (2) dual step on row i
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            PHN[P][k] = fma(c.beta, fma(c.theta, AN[P][k] - RV[P][k], AN[P][k]), PH[P][k]);
+        {
+            T w[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? PHN[P][k] : T(0);
+            bstore(c.phio, so_i, w);
+#pragma unroll
+            for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? AN[P][k] : T(0);
+            bstore(c.ro, so_i, w);
+        }
+        if constexpr (!HEAD) {
+            // (3) primal update of row i + 1 with phi_n of rows i + 1 and i
+            const int in = i + 1;
+            const bool own_n = (in >= c.r0) && (in < c.rend);
+            const uint32_t so_n = c.vb_st + (own_n ? (uint32_t)in * c.row_bytes : OOB);
+            const T ph_prev = __shfl_up(PHN[Q][V - 1], 1, WAVE);
+            const T wgx = in > 0 ? c.idx : T(0);
+            T u1x[V], u1t[V];
+            T l1 = T(0), l2 = T(0);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const T gx = (PHN[Q][k] - PHN[P][k]) * wgx;
+                const T pprev = (k > 0) ? PHN[Q][(k + V - 1) % V] : ph_prev;
+                T gt = (PHN[Q][k] - pprev) * c.idt;
+                if constexpr (EDGE) gt = c.jgt0[k] ? gt : T(0);
+                u1x[k] = shrink_scaled(fma(c.alpha, gx, UX[X3][k]), c.alpha, c.inv);
+                u1t[k] = shrink_scaled(fma(c.alpha, gt, UT[X3][k]), c.alpha, c.inv);
+                DX[P][k] = u1x[k] - UX[X3][k];
+                DT[P][k] = u1t[k] - UT[X3][k];
+                if (!EDGE || c.inb[k]) {
+                    l1 += fabs(u1x[k]) + fabs(u1t[k]);
+                    l2 = fma(u1x[k], u1x[k], fma(u1t[k], u1t[k], l2));
+                }
+            }
+            {
+                T w[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? u1x[k] : T(0);
+                bstore(c.uxo, so_n, w);
+#pragma unroll
+                for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? u1t[k] : T(0);
+                bstore(c.uto, so_n, w);
+            }
+            if (own_n && c.lane_out) {
+                acc[6] += double(l1);
+                acc[7] += double(l2);
+            }
+            // (4) residual of the new flux on row i + 1
+            close_row<P>(in);
+        }
+    }
+
+    // the march from row ib up to ibeg (to the virtual row -1 at the top of the grid)
+    __device__ __forceinline__ void run()
+    {
+        const int itop = c.ibeg > 0 ? c.ibeg : -1;
+        int i = ib;
+        step<0, true>(i--);
+        for (; i - 3 >= itop; i -= 4) {
+            step<1, false>(i);
+            step<2, false>(i - 1);
+            step<3, false>(i - 2);
+            step<0, false>(i - 3);
+        }
+        if (i >= itop) {
+            step<1, false>(i--);
+            if (i >= itop) {
+                step<2, false>(i--);
+                if (i >= itop) step<3, false>(i--);
+            }
+        }
+    }
+};
+
 // One tile: set up the lane's view, put the first rows in flight, then take the
 // gather's decision (which reduces the previous sweep's partials) while they load.
-template <typename T, bool EDGE>
+// UP: the tile marches up its rows (odd strips, see PipeUp); the last sweep of a
+// gather (dual step only) always marches down.
+template <typename T, bool EDGE, bool UP>
 __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p)
 {
     constexpr int V = Vec<T>::N;
@@ -507,7 +732,8 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     c.phio = rs(a.phi[q]);
     c.ro = rs(a.R[q]);
 
-    Pipe<T, EDGE> P(c);
+    using Pipeline = typename std::conditional<UP, PipeUp<T, EDGE>, Pipe<T, EDGE>>::type;
+    Pipeline P(c);
     P.start();
     const Decision d = decide(a, p, tl.g, gm, tl.slot == gm.tile_base);
     if (!d.run) return;
@@ -516,7 +742,8 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     P.c.alpha = T(d.alpha);
     P.c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
     if (d.prox) {
-        P.template run<true>();
+        if constexpr (UP) P.run();
+        else P.template run<true>();
 #pragma unroll
         for (int m = 0; m < NPART; ++m) P.acc[m] = wave_sum(P.acc[m]);
         if (lane == 0) {
@@ -524,6 +751,10 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
 #pragma unroll
             for (int m = 0; m < NPART; ++m) dst[m] = P.acc[m];
         }
+    } else if constexpr (UP) {
+        Pipe<T, EDGE> D(P.c);
+        D.start();
+        D.template run<false>();
     } else {
         P.template run<false>();
     }
@@ -548,8 +779,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     // tiles whose loaded lanes (0..OUT_LANES + 1) all sit strictly inside (0, nt - 1)
     // need no time-boundary masks
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
-    if (edge) sweep_tile<T, true>(a, tl, gm, parity);
-    else sweep_tile<T, false>(a, tl, gm, parity);
+    // odd strips march up
+    const bool up = ((tl.r0 / a.rows) & 1) != 0;
+    if (edge) {
+        if (up) sweep_tile<T, true, true>(a, tl, gm, parity);
+        else sweep_tile<T, true, false>(a, tl, gm, parity);
+    } else {
+        if (up) sweep_tile<T, false, true>(a, tl, gm, parity);
+        else sweep_tile<T, false, false>(a, tl, gm, parity);
+    }
 }
 
 template <typename T>
