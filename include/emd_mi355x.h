@@ -95,9 +95,11 @@ typedef struct {
  *   tol_res: stop when ||div u + s||_2 / ||s||_2 <= tol_res, checked every
  *     check_every iterations (this certifies feasibility, not optimality).
  *   ls_mode: EMD_LS_L2 uses Euclidean norms in the linesearch test (the
- *     Malitsky-Pock setting); EMD_LS_L1 the l1 norms printed in Algorithm 1
- *     (returns EMD_ERR_UNSUPPORTED in this build); EMD_LS_FIXED is plain PDHG with
- *     theta = 1 and the fixed steps alpha_1, beta_1 = delta alpha_1.
+ *     Malitsky-Pock setting); EMD_LS_L1 the l1 norms printed in Algorithm 1 (each
+ *     sweep sums the test for the first 6 backtracking candidates of the next
+ *     iteration; should all 6 fail, one extra sweep without an iteration sums the
+ *     next 6); EMD_LS_FIXED is plain PDHG with theta = 1 and the fixed steps
+ *     alpha_1, beta_1 = delta alpha_1.
  *   mass_mode: how emd_decompose builds s (see there) and emd_adjoint_source chains.
  *   precision: element type of all field buffers (EMD_F32: float fields, FP64
  *     reductions and scalars; EMD_F64: double throughout).

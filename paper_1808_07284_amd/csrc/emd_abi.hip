@@ -68,7 +68,8 @@ struct emd_plan {
     Tile* d_tiles = nullptr;      // every gather's tiles (auxiliary kernels, first chunk)
     Tile* d_tiles_act = nullptr;  // the running gathers' tiles, rebuilt as gathers finish
     void* d_fields = nullptr;  // one allocation: s, ux[2], ut[2], phi[2], R[2]
-    double* d_part = nullptr;  // [2][tiles][NPART]
+    double* d_part = nullptr;     // [2][slots][NPART]
+    double* d_part_l1 = nullptr;  // [2][slots][NPART_L1] (l1 linesearch test)
     GState* d_gst = nullptr;   // [2][ngather]
     int32_t* d_done = nullptr;
     double* d_adj = nullptr;   // [ngather][4]
@@ -119,8 +120,6 @@ emd_status validate_params(const emd_params* p)
     if (p->precision != EMD_F32 && p->precision != EMD_F64) return bad("unknown precision");
     if (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096)
         return bad("sweeps_per_sync must lie in [2, 4096]");
-    if (p->ls_mode == EMD_LS_L1)
-        return fail(EMD_ERR_UNSUPPORTED, "the l1 linesearch test is not implemented on the GPU");
     return EMD_SUCCESS;
 }
 
@@ -241,12 +240,15 @@ emd_status build_tiles(emd_plan* plan)
         if (plan->d_tiles) (void)hipFree(plan->d_tiles);
         if (plan->d_tiles_act) (void)hipFree(plan->d_tiles_act);
         if (plan->d_part) (void)hipFree(plan->d_part);
+        if (plan->d_part_l1) (void)hipFree(plan->d_part_l1);
         plan->d_tiles = nullptr;
         plan->d_tiles_act = nullptr;
         plan->d_part = nullptr;
+        plan->d_part_l1 = nullptr;
         if (hipMalloc(&plan->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
             hipMalloc(&plan->d_tiles_act, sizeof(Tile) * tiles.size()) != hipSuccess ||
-            hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * slots) != hipSuccess)
+            hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * slots) != hipSuccess ||
+            hipMalloc(&plan->d_part_l1, sizeof(double) * NPART_L1 * 2 * slots) != hipSuccess)
             return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate the tile table");
     }
     if (!plan->d_meta && hipMalloc(&plan->d_meta, sizeof(GatherMeta) * plan->ngather) != hipSuccess)
@@ -254,6 +256,7 @@ emd_status build_tiles(emd_plan* plan)
     HIP_TRY(hipMemcpy(plan->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(plan->d_meta, meta.data(), sizeof(GatherMeta) * meta.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(plan->d_part, 0, sizeof(double) * NPART * 2 * slots));
+    HIP_TRY(hipMemset(plan->d_part_l1, 0, sizeof(double) * NPART_L1 * 2 * slots));
     destroy_graph(plan);
     return EMD_SUCCESS;
 }
@@ -326,10 +329,13 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
         a.ut[b] = field<T>(plan, 3 + b);
         a.phi[b] = field<T>(plan, 5 + b);
         a.R[b] = field<T>(plan, 7 + b);
-        a.part[b] = plan->d_part + (int64_t)b * plan->nslots * NPART;
+        a.part[b] = sc.ls_mode == LS_L1 ? plan->d_part_l1 + (int64_t)b * plan->nslots * NPART_L1
+                                        : plan->d_part + (int64_t)b * plan->nslots * NPART;
         a.gst[b] = plan->d_gst + (int64_t)b * plan->ngather;
     }
     a.done = plan->d_done;
+    a.l1 = sc.ls_mode == LS_L1;
+    a.pad = 0;
     a.sc = sc;
     return a;
 }
@@ -397,8 +403,10 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
     int grid = plan->grid;
     const int chunk = plan->params.sweeps_per_sync;
-    // a gather needs iters + 1 sweeps; the last one applies the final dual step
-    const int64_t max_sweeps = round_up((int64_t)plan->params.max_iter + 2, 2);
+    // a gather needs iters + 1 sweeps, the last one applying the final dual step;
+    // the l1 test may add an evaluation sweep per NL1 failed backtracking trials
+    const int64_t evals = ls_mode == LS_L1 ? plan->params.max_ls_trials / NL1 + 1 : 0;
+    const int64_t max_sweeps = round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
     int64_t sweeps = 0;
     // Finished gathers leave the sweep's tile table: once the running gathers hold at
     // most 7/8 of the table's cells, the table is rebuilt from them alone and spread
@@ -583,7 +591,7 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
         return fail(EMD_ERR_HIP, "workspace initialisation failed");
     }
     plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
-                            (int64_t)sizeof(double) * NPART * 2 * plan->nslots +
+                            (int64_t)sizeof(double) * (NPART + NPART_L1) * 2 * plan->nslots +
                             (int64_t)sizeof(Tile) * 2 * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
     *out = plan;
     return EMD_SUCCESS;
@@ -599,6 +607,7 @@ emd_status emd_plan_destroy(emd_plan* plan)
     if (plan->d_tiles_act) (void)hipFree(plan->d_tiles_act);
     if (plan->d_fields) (void)hipFree(plan->d_fields);
     if (plan->d_part) (void)hipFree(plan->d_part);
+    if (plan->d_part_l1) (void)hipFree(plan->d_part_l1);
     if (plan->d_gst) (void)hipFree(plan->d_gst);
     if (plan->d_done) (void)hipFree(plan->d_done);
     if (plan->d_adj) (void)hipFree(plan->d_adj);

@@ -116,6 +116,8 @@ __global__ __launch_bounds__(64) void k_gather_init(AuxArgs<T> a)
     st.started = 0;
     st.ubuf = 0;
     st.phibuf = 0;
+    st.flip = 0;
+    st.ls_base = 0;
     int status = ST_RUNNING;
     if (q[1] != 0.0 || !isfinite(st.snorm)) {
         status = ST_NONFINITE;

@@ -34,6 +34,12 @@ enum : int { MASS_BALANCE = 0, MASS_UNIT = 1, MASS_NONE = 2 };
 // <A,A>, <A,B>, <B,B>, <grad A,grad A>, <grad A,grad B>, <grad B,grad B>,
 // sum |u|, sum u^2 (A = div u_new + s, B = A - previous A).
 constexpr int NPART = 8;
+// The l1 linesearch test is not a quadratic form in theta, so a sweep sums it for
+// NL1 candidate steps at once.  Record layout (NPART_L1 doubles): <A,A>, sum |u|,
+// sum u^2, 0, then sum |A + theta_m B| and sum |grad (A + theta_m B)| for the NL1
+// candidates theta_m.
+constexpr int NL1 = 6;
+constexpr int NPART_L1 = 16;
 constexpr int WAVE = 64;
 // A sweep wave owns OUT_LANES * V consecutive time samples in lanes 1..OUT_LANES;
 // lanes 0 and OUT_LANES + 1 carry the time-axis halo, the remaining lanes idle.
@@ -73,6 +79,8 @@ struct GState {
     int32_t started;   // 0 until the first primal update has been applied
     int32_t ubuf;      // buffer holding the returned u once status != RUNNING
     int32_t phibuf;    // buffer holding the returned phi once status != RUNNING
+    int32_t flip;      // the gather's fields sit in buffers (sweep parity ^ flip)
+    int32_t ls_base;   // l1 linesearch: index of the first candidate in the partials
 };
 
 struct SolveScalars {
@@ -95,24 +103,33 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum n records of NPART doubles (record p at src[p * NPART]) in a fixed order:
-// lane l adds records l, l + 64, ... in sequence, then the butterfly.
+// Sum n records of NP doubles (record p at src[p * NP]) in a fixed order: lane l
+// adds records l, l + 64, ... in sequence, then the butterfly.
+template <int NP>
 __device__ __forceinline__ void reduce_records(const double* __restrict__ src, int n,
-                                               double out[NPART])
+                                               double (&out)[NP])
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    double acc[NPART];
+    double acc[NP];
 #pragma unroll
-    for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
     for (int p = lane; p < n; p += WAVE) {
 #pragma unroll
-        for (int q = 0; q < NPART; ++q) acc[q] += src[(int64_t)p * NPART + q];
+        for (int q = 0; q < NP; ++q) acc[q] += src[(int64_t)p * NP + q];
     }
 #pragma unroll
-    for (int q = 0; q < NPART; ++q) out[q] = wave_sum(acc[q]);
+    for (int q = 0; q < NP; ++q) out[q] = wave_sum(acc[q]);
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A double every lane holds the same value of, moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).  Give
 // each XCD a contiguous range of logical blocks (one run of the tile table), so that

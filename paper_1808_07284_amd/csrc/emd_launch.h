@@ -18,9 +18,10 @@ struct SweepArgs {
     T* ut[2];
     T* phi[2];
     T* R[2];
-    double* part[2];       // [tiles][NPART] partial sums, by sweep parity
+    double* part[2];       // [slots][NPART or NPART_L1] partial sums, by sweep parity
     GState* gst[2];        // [ngather], by sweep parity
     int32_t* done;         // gathers that have finished
+    int32_t l1, pad;       // 1: the l1 form of the linesearch test
     SolveScalars sc;
 };
 

@@ -43,22 +43,42 @@ struct Decision {
     double theta;
     int run;       // 0: gather finished, nothing to do
     int prox;      // 1: compute the next primal iterate and its reductions
+    int eval;      // 1 (l1 test only): no candidate passed; re-evaluate the next ones
+    double cand0;  // l1 test: first candidate step of the next decision ...
+    double cand_ref;  // ... and the step its theta is relative to
 };
 
+// First candidate step of a linesearch from step ak and theta tk, after `skip`
+// backtracking factors; the sweep and the decision compute the candidates with
+// the same operations, so they agree bitwise.
+__device__ __forceinline__ double first_candidate(double ak, double tk, double amax, double xi, int skip)
+{
+    double alpha = ak * sqrt(1.0 + tk);
+    if (alpha > amax) alpha = amax;
+    for (int m = 0; m < skip; ++m) alpha *= xi;
+    return alpha;
+}
+
 // Runs on every lane of a wave; returns the same decision on every lane.
-template <typename T>
+// ABS: the l1 form of the linesearch test (records of NPART_L1 doubles).
+// pb: buffer parity of the gather's fields in this sweep.
+template <typename T, bool ABS>
 __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta& gm,
-                           bool writer)
+                           bool writer, int pb)
 {
     const GState* __restrict__ sin = a.gst[p] + g;
     GState* __restrict__ sout = a.gst[p ^ 1] + g;
     GState st = *sin;
+    const SolveScalars& sc = a.sc;
     Decision d;
     d.alpha = st.alpha;
     d.beta = 0.0;
     d.theta = 0.0;
     d.run = 0;
     d.prox = 0;
+    d.eval = 0;
+    d.cand0 = 0.0;
+    d.cand_ref = 1.0;
     const int lane = threadIdx.x & (WAVE - 1);
     if (st.status != ST_RUNNING) {
         if (writer && lane == 0) *sout = st;
@@ -70,21 +90,62 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
         if (writer && lane == 0) *sout = st;
         d.run = 1;
         d.prox = 1;
+        if constexpr (ABS) {
+            d.cand0 = first_candidate(st.alpha, st.theta, st.alpha_max, sc.xi, 0);
+            d.cand_ref = st.alpha;
+        }
         return d;
     }
-    double q[NPART];
-    reduce_records(a.part[p] + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
-    const double aa = q[0], ab = q[1], bb = q[2], gaa = q[3], gab = q[4], gbb = q[5];
-    const double l1 = q[6], l2 = q[7];
-    const SolveScalars& sc = a.sc;
+    constexpr int NP = ABS ? NPART_L1 : NPART;
+    double q[NP];
+    reduce_records(a.part[p] + (int64_t)gm.tile_base * NP, gm.ntiles, q);
+    const double aa = q[0];
+    const double l1 = ABS ? q[1] : q[6], l2 = ABS ? q[2] : q[7];
     const double ak = st.alpha, tk = st.theta;
     double alpha, theta = 1.0;
     int trials = 0, status = ST_RUNNING;
-    bool finite = isfinite(aa) && isfinite(ab) && isfinite(bb) && isfinite(gaa) &&
-                  isfinite(gab) && isfinite(gbb) && isfinite(l1) && isfinite(l2);
+    bool finite = true;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) finite = finite && isfinite(q[m]);
     if (!finite) {
         status = ST_NONFINITE;
         alpha = ak;
+    } else if constexpr (ABS) {
+        // candidates ls_base, ls_base + 1, ... of this iteration's backtracking:
+        //   sqrt(delta) alpha ||grad rbar||_1 <= zeta ||rbar||_1,  rbar = A + theta B
+        alpha = first_candidate(ak, tk, st.alpha_max, sc.xi, st.ls_base);
+        const double sd = sqrt(sc.delta);
+        bool found = false;
+        for (int m = 0; m < NL1 && status == ST_RUNNING; ++m) {
+            theta = alpha / ak;
+            const double lhs = sd * alpha * q[4 + NL1 + m];
+            const double rhs = sc.zeta * q[4 + m];
+            if (!(isfinite(lhs) && isfinite(rhs))) {
+                status = ST_NONFINITE;
+                break;
+            }
+            if (lhs <= rhs) {
+                found = true;
+                break;
+            }
+            alpha *= sc.xi;
+            ++trials;
+            if (st.ls_base + trials > sc.max_ls_trials) status = ST_LS_FAIL;
+        }
+        if (!found && status == ST_RUNNING) {
+            // every candidate of the record failed: an evaluation sweep sums the
+            // next NL1 for the same flux; the fields stay where they are, so the
+            // following sweep reads the other buffer parity
+            st.trials += trials;
+            st.ls_base += NL1;
+            st.flip ^= 1;
+            if (writer && lane == 0) *sout = st;
+            d.run = 1;
+            d.eval = 1;
+            d.cand0 = first_candidate(ak, tk, st.alpha_max, sc.xi, st.ls_base);
+            d.cand_ref = ak;
+            return d;
+        }
     } else if (sc.ls_mode == LS_FIXED) {
         alpha = ak;
         theta = 1.0;
@@ -92,6 +153,7 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
         alpha = sc.replay[(int64_t)g * sc.ld_replay + st.iters];
         theta = alpha / ak;
     } else {
+        const double ab = q[1], bb = q[2], gaa = q[3], gab = q[4], gbb = q[5];
         alpha = ak * sqrt(1.0 + tk);
         if (alpha > st.alpha_max) alpha = st.alpha_max;
         for (;;) {
@@ -112,7 +174,8 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
         }
     }
     st.trials += trials;
-    const int p1 = p ^ 1;
+    st.ls_base = 0;
+    const int qb = pb ^ 1;
     if (status == ST_RUNNING) {
         // accept iteration st.iters + 1: phi_n is written by this sweep, u_n is the
         // flux this sweep reads
@@ -129,13 +192,17 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
         d.alpha = alpha;
         d.beta = sc.delta * alpha;
         d.theta = theta;
-        st.ubuf = p;
-        st.phibuf = p1;
+        st.ubuf = pb;
+        st.phibuf = qb;
+        if constexpr (ABS) {
+            d.cand0 = first_candidate(alpha, theta, st.alpha_max, sc.xi, 0);
+            d.cand_ref = alpha;
+        }
     } else {
         // the trial step is rejected: return the last accepted iterate (u_{n-1} is
         // still in the buffer this sweep would have written, phi_{n-1} in its input)
-        st.ubuf = p1;
-        st.phibuf = p;
+        st.ubuf = qb;
+        st.phibuf = pb;
     }
     st.status = status;
     if (writer && lane == 0) {
@@ -181,6 +248,7 @@ struct TileCtx {
     bool lane_out;
     bool inb[V], jgt0[V], jlt[V];
     T idx, idt, beta, theta, alpha, inv;
+    double thm[NL1];               // l1 linesearch: candidate thetas of the next decision
     uint32_t row_bytes;            // ld * sizeof(T)
     uint32_t vb_ld, vb_st;         // lane byte offsets for loads / stores (or OOB)
     __amdgpu_buffer_rsrc_t uxi, uti, phi_i, ri, si, uxo, uto, phio, ro;
@@ -249,6 +317,43 @@ __device__ __forceinline__ void div_row(const TileCtx<T>& c, bool has_next, bool
     }
 }
 
+// Partial sums of one residual cell of the new flux, a = A_{n+1} and b = B_{n+1}:
+// the cell's own terms and its time-gradient terms (gat, gbt) ...
+template <bool ABS, int NP>
+__device__ __forceinline__ void acc_cell(double (&acc)[NP], const double (&thm)[NL1], double av,
+                                         double bv, double gat, double gbt)
+{
+    acc[0] = fma(av, av, acc[0]);
+    if constexpr (ABS) {
+#pragma unroll
+        for (int m = 0; m < NL1; ++m) {
+            acc[4 + m] += fabs(fma(thm[m], bv, av));
+            acc[4 + NL1 + m] += fabs(fma(thm[m], gbt, gat));
+        }
+    } else {
+        acc[1] = fma(av, bv, acc[1]);
+        acc[2] = fma(bv, bv, acc[2]);
+        acc[3] = fma(gat, gat, acc[3]);
+        acc[4] = fma(gat, gbt, acc[4]);
+        acc[5] = fma(gbt, gbt, acc[5]);
+    }
+}
+
+// ... and its x-gradient terms (gax, gbx)
+template <bool ABS, int NP>
+__device__ __forceinline__ void acc_xgrad(double (&acc)[NP], const double (&thm)[NL1], double gax,
+                                          double gbx)
+{
+    if constexpr (ABS) {
+#pragma unroll
+        for (int m = 0; m < NL1; ++m) acc[4 + NL1 + m] += fabs(fma(thm[m], gbx, gax));
+    } else {
+        acc[3] = fma(gax, gax, acc[3]);
+        acc[4] = fma(gax, gbx, acc[4]);
+        acc[5] = fma(gbx, gbx, acc[5]);
+    }
+}
+
 // The row pipeline of one wavefront.  Every per-row quantity lives in register
 // sets indexed by the row's position relative to the first row (mod 4 for u^x,
 // mod 2 for everything else), and the loop is unrolled by four, so no register is
@@ -259,16 +364,18 @@ __device__ __forceinline__ void div_row(const TileCtx<T>& c, bool has_next, bool
 // new flux on row i - 1 needs only the flux change of rows i - 1 and i and A_n of
 // row i - 1 (B is formed from the small flux change instead of as a difference of
 // two nearly equal residuals).
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool ABS>
 struct Pipe {
     static constexpr int V = Vec<T>::N;
+    static constexpr int NP = ABS ? NPART_L1 : NPART;
+    static constexpr int IL1 = ABS ? 1 : 6, IL2 = ABS ? 2 : 7;  // sum |u|, sum u^2
     TileCtx<T> c;
     T UX[4][V];                              // u^x_n
     T UT[2][V], PH[2][V], SV[2][V], RV[2][V];  // u^t_n, phi_{n-1}, s, R
     T PHN[2][V], AN[2][V];   // phi_n and A_n = div u_n + s
     T DX[2][V], DT[2][V];    // u_{n+1} - u_n
     T A1[2][V], B1[2][V];    // A_{n+1}, B_{n+1} (one row behind)
-    double acc[NPART];
+    double acc[NP];
 
     __device__ explicit Pipe(const TileCtx<T>& ctx) : c(ctx)
     {
@@ -277,7 +384,7 @@ struct Pipe {
             zero(PHN[b]); zero(AN[b]); zero(DX[b]); zero(DT[b]); zero(A1[b]); zero(B1[b]);
         }
 #pragma unroll
-        for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+        for (int m = 0; m < NP; ++m) acc[m] = 0.0;
     }
 
     // byte offset of row i for loads (rows past the grid fall out of range)
@@ -338,12 +445,17 @@ struct Pipe {
                     gbt = c.jgt0[k] ? gbt : 0.0;
                 }
                 const double av = double(a[k]), bv = double(b[k]);
-                acc[0] = fma(av, av, acc[0]);
-                acc[1] = fma(av, bv, acc[1]);
-                acc[2] = fma(bv, bv, acc[2]);
-                acc[3] = fma(gax, gax, fma(gat, gat, acc[3]));
-                acc[4] = fma(gax, gbx, fma(gat, gbt, acc[4]));
-                acc[5] = fma(gbx, gbx, fma(gbt, gbt, acc[5]));
+                if constexpr (ABS) {
+                    acc_cell<true>(acc, c.thm, av, bv, gat, gbt);
+                    acc_xgrad<true>(acc, c.thm, gax, gbx);
+                } else {
+                    acc[0] = fma(av, av, acc[0]);
+                    acc[1] = fma(av, bv, acc[1]);
+                    acc[2] = fma(bv, bv, acc[2]);
+                    acc[3] = fma(gax, gax, fma(gat, gat, acc[3]));
+                    acc[4] = fma(gax, gbx, fma(gat, gbt, acc[4]));
+                    acc[5] = fma(gbx, gbx, fma(gbt, gbt, acc[5]));
+                }
             }
         }
 #pragma unroll
@@ -415,8 +527,8 @@ struct Pipe {
                 bstore(c.uto, so, w);
             }
             if (own_row && c.lane_out) {
-                acc[6] += double(l1);
-                acc[7] += double(l2);
+                acc[IL1] += double(l1);
+                acc[IL2] += double(l2);
             }
             // (4) residual of the new flux on row i - 1
             if (i > c.ibeg) close_row<Q>(i - 1, DX[P], true);
@@ -486,9 +598,11 @@ struct Pipe {
 // one step earlier.  The march ends at a virtual row -1 when it reaches the top of
 // the grid, so that row 0 gets its flux update and residual (nothing is loaded or
 // stored for row -1, and its gradient weight is zero).
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool ABS>
 struct PipeUp {
     static constexpr int V = Vec<T>::N;
+    static constexpr int NP = ABS ? NPART_L1 : NPART;
+    static constexpr int IL1 = ABS ? 1 : 6, IL2 = ABS ? 2 : 7;
     TileCtx<T> c;
     int ib;                                // bottom row of the march
     T UX[4][V], UT[4][V];                  // u_n: row i in set S, i + 1 in S + 3
@@ -496,7 +610,7 @@ struct PipeUp {
     T PHN[2][V], AN[2][V];                 // phi_n, A_n: row i (P), row i + 1 (Q)
     T DX[2][V], DT[2][V];                  // u_{n+1} - u_n: row i + 1 (P), row i + 2 (Q)
     T A1[V], B1[V];                        // A_{n+1}, B_{n+1} of the last residual row
-    double acc[NPART];
+    double acc[NP];
 
     __device__ explicit PipeUp(const TileCtx<T>& ctx) : c(ctx)
     {
@@ -508,7 +622,7 @@ struct PipeUp {
         zero(A1);
         zero(B1);
 #pragma unroll
-        for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+        for (int m = 0; m < NP; ++m) acc[m] = 0.0;
     }
 
     __device__ __forceinline__ uint32_t lrow(int i) const { return c.vb_ld + (uint32_t)i * c.row_bytes; }
@@ -569,20 +683,12 @@ struct PipeUp {
                         gat = c.jgt0[k] ? gat : 0.0;
                         gbt = c.jgt0[k] ? gbt : 0.0;
                     }
-                    const double av = double(a[k]), bv = double(b[k]);
-                    acc[0] = fma(av, av, acc[0]);
-                    acc[1] = fma(av, bv, acc[1]);
-                    acc[2] = fma(bv, bv, acc[2]);
-                    acc[3] = fma(gat, gat, acc[3]);
-                    acc[4] = fma(gat, gbt, acc[4]);
-                    acc[5] = fma(gbt, gbt, acc[5]);
+                    acc_cell<ABS>(acc, c.thm, double(a[k]), double(b[k]), gat, gbt);
                 }
                 if (own_below) {
                     const double gax = double((A1[k] - a[k]) * c.idx);
                     const double gbx = double((B1[k] - b[k]) * c.idx);
-                    acc[3] = fma(gax, gax, acc[3]);
-                    acc[4] = fma(gax, gbx, acc[4]);
-                    acc[5] = fma(gbx, gbx, acc[5]);
+                    acc_xgrad<ABS>(acc, c.thm, gax, gbx);
                 }
             }
         }
@@ -655,8 +761,8 @@ struct PipeUp {
                 bstore(c.uto, so_n, w);
             }
             if (own_n && c.lane_out) {
-                acc[6] += double(l1);
-                acc[7] += double(l2);
+                acc[IL1] += double(l1);
+                acc[IL2] += double(l2);
             }
             // (4) residual of the new flux on row i + 1
             close_row<P>(in);
@@ -685,16 +791,87 @@ struct PipeUp {
     }
 };
 
+// Evaluation sweep of the l1 linesearch, for a gather none of whose NL1 candidates
+// passed: recompute, exactly as the previous sweep formed them, the residual
+// A_n = A_{n-1} + div(u_n - u_{n-1}) and B_n = div(u_n - u_{n-1}) from u_n (the
+// input buffers) and u_{n-1} (the output buffers, which this sweep leaves alone),
+// and sum the test for the next NL1 candidates together with <A,A>, sum |u_n| and
+// sum u_n^2.  Rare, so one plain row at a time; no field is written.
+template <typename T>
+__device__ void eval_tile(const TileCtx<T>& c, double (&acc)[NPART_L1])
+{
+    constexpr int V = Vec<T>::N;
+#pragma unroll
+    for (int m = 0; m < NPART_L1; ++m) acc[m] = 0.0;
+    T a_up[V], b_up[V];  // A_n, B_n of the row above
+    zero(a_up);
+    zero(b_up);
+    T zero_add[V];
+    zero(zero_add);
+    for (int im = max(c.r0 - 1, 0); im < c.rend; ++im) {
+        const uint32_t o0 = c.vb_ld + (uint32_t)im * c.row_bytes;
+        const uint32_t o1 = o0 + c.row_bytes;  // row im + 1: out of range past the grid
+        T nx0[V], nt0[V], nx1[V], ox0[V], ot0[V], ox1[V], sv[V];
+        bload(c.uxi, o0, nx0);
+        bload(c.uti, o0, nt0);
+        bload(c.uxi, o1, nx1);
+        bload(c.uxo, o0, ox0);
+        bload(c.uto, o0, ot0);
+        bload(c.uxo, o1, ox1);
+        bload(c.si, o0, sv);
+        T an[V], dx0[V], dx1[V], dt0[V], b[V], a[V];
+        div_row<T, true>(c, im + 1 < c.nr, im > 0, ox0, ox1, ot0, __shfl_down(ot0[0], 1, WAVE), sv, an);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            dx0[k] = nx0[k] - ox0[k];
+            dx1[k] = nx1[k] - ox1[k];
+            dt0[k] = nt0[k] - ot0[k];
+        }
+        div_row<T, true>(c, im + 1 < c.nr, im > 0, dx0, dx1, dt0, __shfl_down(dt0[0], 1, WAVE), zero_add, b);
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[k] = an[k] + b[k];
+        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
+        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        if (im >= c.r0 && c.lane_out) {
+            const bool xg = im > 0;
+            T l1 = T(0), l2 = T(0);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (!c.inb[k]) continue;
+                const T ap = (k > 0) ? a[(k + V - 1) % V] : a_prev;
+                const T bp = (k > 0) ? b[(k + V - 1) % V] : b_prev;
+                const double gat = c.jgt0[k] ? double((a[k] - ap) * c.idt) : 0.0;
+                const double gbt = c.jgt0[k] ? double((b[k] - bp) * c.idt) : 0.0;
+                const double gax = xg ? double((a[k] - a_up[k]) * c.idx) : 0.0;
+                const double gbx = xg ? double((b[k] - b_up[k]) * c.idx) : 0.0;
+                acc_cell<true>(acc, c.thm, double(a[k]), double(b[k]), gat, gbt);
+                acc_xgrad<true>(acc, c.thm, gax, gbx);
+                l1 += fabs(nx0[k]) + fabs(nt0[k]);
+                l2 = fma(nx0[k], nx0[k], fma(nt0[k], nt0[k], l2));
+            }
+            acc[1] += double(l1);
+            acc[2] += double(l2);
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            a_up[k] = a[k];
+            b_up[k] = b[k];
+        }
+    }
+}
+
 // One tile: set up the lane's view, put the first rows in flight, then take the
 // gather's decision (which reduces the previous sweep's partials) while they load.
 // UP: the tile marches up its rows (odd strips, see PipeUp); the last sweep of a
-// gather (dual step only) always marches down.
-template <typename T, bool EDGE, bool UP>
-__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p)
+// gather (dual step only) always marches down.  ABS: l1 linesearch test.
+// p: sweep parity (partials, scalar state); pb: buffer parity of the fields.
+template <typename T, bool EDGE, bool UP, bool ABS>
+__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb)
 {
     constexpr int V = Vec<T>::N;
+    constexpr int NP = ABS ? NPART_L1 : NPART;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int q = p ^ 1;
+    const int q = p ^ 1, qb = pb ^ 1;
     TileCtx<T> c;
     c.nr = gm.nr;
     c.ld = gm.ld;
@@ -722,37 +899,60 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     auto rs = [&](const T* f) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f + gm.poff), 0, bytes, 0x00020000);
     };
-    c.uxi = rs(a.ux[p]);
-    c.uti = rs(a.ut[p]);
-    c.phi_i = rs(a.phi[p]);
-    c.ri = rs(a.R[p]);
+    c.uxi = rs(a.ux[pb]);
+    c.uti = rs(a.ut[pb]);
+    c.phi_i = rs(a.phi[pb]);
+    c.ri = rs(a.R[pb]);
     c.si = rs(a.s);
-    c.uxo = rs(a.ux[q]);
-    c.uto = rs(a.ut[q]);
-    c.phio = rs(a.phi[q]);
-    c.ro = rs(a.R[q]);
+    c.uxo = rs(a.ux[qb]);
+    c.uto = rs(a.ut[qb]);
+    c.phio = rs(a.phi[qb]);
+    c.ro = rs(a.R[qb]);
 
-    using Pipeline = typename std::conditional<UP, PipeUp<T, EDGE>, Pipe<T, EDGE>>::type;
+    using Pipeline = typename std::conditional<UP, PipeUp<T, EDGE, ABS>, Pipe<T, EDGE, ABS>>::type;
     Pipeline P(c);
     P.start();
-    const Decision d = decide(a, p, tl.g, gm, tl.slot == gm.tile_base);
+    const Decision d = decide<T, ABS>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb);
     if (!d.run) return;
     P.c.beta = T(d.beta);
     P.c.theta = T(d.theta);
     P.c.alpha = T(d.alpha);
     P.c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    if constexpr (ABS) {
+        // the candidate thetas of the next decision, as it will form them
+        double alpha = uniform_d(d.cand0);
+        const double ref = uniform_d(d.cand_ref);
+#pragma unroll
+        for (int m = 0; m < NL1; ++m) {
+            P.c.thm[m] = alpha / ref;
+            alpha *= a.sc.xi;
+        }
+    }
+    double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NP;
+    if constexpr (ABS) {
+        if (d.eval) {
+            double acc[NPART_L1];
+            eval_tile<T>(P.c, acc);
+#pragma unroll
+            for (int m = 0; m < NPART_L1; ++m) acc[m] = wave_sum(acc[m]);
+            if (lane == 0) {
+#pragma unroll
+                for (int m = 0; m < NPART_L1; ++m) dst[m] = acc[m];
+            }
+            return;
+        }
+    }
     if (d.prox) {
         if constexpr (UP) P.run();
         else P.template run<true>();
 #pragma unroll
-        for (int m = 0; m < NPART; ++m) P.acc[m] = wave_sum(P.acc[m]);
+        for (int m = 0; m < NP; ++m) P.acc[m] = wave_sum(P.acc[m]);
         if (lane == 0) {
-            double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
 #pragma unroll
-            for (int m = 0; m < NPART; ++m) dst[m] = P.acc[m];
+            for (int m = 0; m < NP; ++m) dst[m] = P.acc[m];
         }
     } else if constexpr (UP) {
-        Pipe<T, EDGE> D(P.c);
+        Pipe<T, EDGE, ABS> D(P.c);
         D.start();
         D.template run<false>();
     } else {
@@ -760,7 +960,7 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     }
 }
 
-template <typename T>
+template <typename T, bool ABS>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
 {
     constexpr int V = Vec<T>::N;
@@ -770,30 +970,35 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     const int g = uniform(tl.g);
     if (g < 0) return;  // padding entry
     const GatherMeta gm = a.meta[g];
-    if (a.gst[parity][g].status != ST_RUNNING) {
+    const GState* gs = a.gst[parity] + g;
+    if (gs->status != ST_RUNNING) {
         // finished gather: only carry its state to the other parity
         if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0)
-            a.gst[parity ^ 1][g] = a.gst[parity][g];
+            a.gst[parity ^ 1][g] = *gs;
         return;
     }
+    const int pb = uniform(parity ^ gs->flip);
     // tiles whose loaded lanes (0..OUT_LANES + 1) all sit strictly inside (0, nt - 1)
     // need no time-boundary masks
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
     // odd strips march up
     const bool up = ((tl.r0 / a.rows) & 1) != 0;
     if (edge) {
-        if (up) sweep_tile<T, true, true>(a, tl, gm, parity);
-        else sweep_tile<T, true, false>(a, tl, gm, parity);
+        if (up) sweep_tile<T, true, true, ABS>(a, tl, gm, parity, pb);
+        else sweep_tile<T, true, false, ABS>(a, tl, gm, parity, pb);
     } else {
-        if (up) sweep_tile<T, false, true>(a, tl, gm, parity);
-        else sweep_tile<T, false, false>(a, tl, gm, parity);
+        if (up) sweep_tile<T, false, true, ABS>(a, tl, gm, parity, pb);
+        else sweep_tile<T, false, false, ABS>(a, tl, gm, parity, pb);
     }
 }
 
 template <typename T>
 void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_sweep<T>, dim3(grid), dim3(256), 0, stream, a, parity);
+    if (a.l1)
+        hipLaunchKernelGGL((k_sweep<T, true>), dim3(grid), dim3(256), 0, stream, a, parity);
+    else
+        hipLaunchKernelGGL((k_sweep<T, false>), dim3(grid), dim3(256), 0, stream, a, parity);
 }
 
 template void launch_sweep<float>(const SweepArgs<float>&, int, int, hipStream_t);

@@ -81,7 +81,8 @@ def _create(L, lib, descs, batch_len, **over):
     ([(2, 5, 1.0, 1.0, 0)], 10, {"precision": 7}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"mass_mode": 3}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 1}, 1),
-    ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 1}, 6),         # l1 test: not on the GPU
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 3}, 1),         # unknown linesearch test
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"max_ls_trials": -1}, 1),
 ])
 def test_plan_create_rejects_bad_arguments(descs, batch, over, code):
     L, lib = _lib()

@@ -86,11 +86,11 @@ def _solve(plan, pcal, pobs, **kw):
     return emd.cpu().numpy(), phi.cpu().numpy(), u.cpu().numpy(), E.info_numpy(info), mass
 
 
-@pytest.mark.parametrize("rows", [8, 32])
-def test_f64_fixed_iterations_match_oracle(rows):
+@pytest.mark.parametrize("rows,ls", [(8, E.LS_L2), (32, E.LS_L2), (8, E.LS_L1), (32, E.LS_L1)])
+def test_f64_fixed_iterations_match_oracle(rows, ls):
     gs = ragged_batch(np.float64)
-    p = E.SolverParams(precision=E.F64, max_iter=300, tol_res=0.0, check_every=300)
-    log(f"f64 fixed K=300 rows={rows}")
+    p = E.SolverParams(precision=E.F64, max_iter=300, tol_res=0.0, check_every=300, ls_mode=ls)
+    log(f"f64 fixed K=300 rows={rows} ls_mode={ls}")
     plan, pcal, pobs, desc = make_plan(gs, p, rows=rows)
     emd, phi, u, info, _ = _solve(plan, pcal, pobs)
     ref = oracle_batch(gs, oracle_params(p))
@@ -109,6 +109,45 @@ def test_f64_fixed_iterations_match_oracle(rows):
         assert rel_l2(phis[k], r.phi) <= 1e-9
         assert rel_l2(us[k][0], r.ux) <= 1e-9 or np.abs(r.ux).max() == 0
         assert rel_l2(us[k][1], r.ut) <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("max_trials", [40, 10])
+def test_l1_backtracking_past_one_sweep_of_candidates(max_trials):
+    # a first step of 1e-2 (50 to 3000 times the safe one on these grids) makes the
+    # first linesearch backtrack 7 to 13 times: more candidates than one sweep sums,
+    # so evaluation sweeps run; with 10 trials allowed some gathers fail there
+    gs = ragged_batch(np.float64)
+    p = E.SolverParams(precision=E.F64, max_iter=60, tol_res=0.0, check_every=60, ls_mode=E.LS_L1,
+                       alpha1=1e-2, max_ls_trials=max_trials)
+    log(f"l1 linesearch, alpha1=1e-2, max_ls_trials={max_trials}")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    emd, phi, u, info, _ = _solve(plan, pcal, pobs)
+    ref = oracle_batch(gs, oracle_params(p), trace=True)
+    phis = unpack(phi, desc)
+    us = unpack(u, desc, 2)
+    first = []
+    for k, (r, _) in enumerate(ref):
+        if r.iters:
+            # backtracking trials of the first linesearch: alpha_2 = 1e-2 sqrt(2) xi^m
+            first.append(int(round(np.log(r.alpha_trace[0] / (1e-2 * np.sqrt(2.0))) / np.log(0.5))))
+        log(f"  gather {k} {gs[k].label}: gpu {info[k]['status']} {info[k]['iters']} {info[k]['ls_trials']} "
+            f"{emd[k]:.12e}  oracle {r.status} {r.iters} {r.ls_trials} {r.emd:.12e}")
+        assert info[k]["status"] == r.status
+        assert info[k]["iters"] == r.iters
+        if r.status == oracle.ZERO_SOURCE:
+            continue
+        assert info[k]["ls_trials"] == r.ls_trials
+        assert emd[k] == pytest.approx(r.emd, rel=1e-9, abs=1e-300)
+        assert info[k]["rel_res"] == pytest.approx(r.rel_res, rel=1e-7)
+        assert rel_l2(phis[k], r.phi) <= 1e-9
+        assert rel_l2(us[k][0], r.ux) <= 1e-9 or np.abs(r.ux).max() == 0
+        assert rel_l2(us[k][1], r.ut) <= 1e-9 or np.abs(r.ut).max() == 0
+    failed = [k for k, (r, _) in enumerate(ref) if r.status == oracle.LS_FAIL]
+    log(f"  first-linesearch trials {first}, failed {failed}")
+    # more than 6 trials (a failure at 10 needed more than 10) needs evaluation sweeps
+    assert any(f > 6 for f in first) or failed
+    assert bool(failed) == (max_trials == 10)
     plan.close()
 
 
@@ -146,7 +185,8 @@ def test_replayed_schedule_matches_oracle(precision):
     plan.close()
 
 
-def test_f32_reaches_the_oracle_optimum():
+@pytest.mark.parametrize("ls", [E.LS_L2, E.LS_L1])
+def test_f32_reaches_the_oracle_optimum(ls):
     # accuracy parity: the oracle runs to a 1e-8 residual (within ~1e-7 of the
     # optimum here); the FP32 solve, free-running with its own linesearch, runs twice
     # as many iterations and must land within 1e-5 of that EMD.  (The residual stop
@@ -155,10 +195,10 @@ def test_f32_reaches_the_oracle_optimum():
     gs = to_precision([config2_gather(nr=24, nt=120, f_peak=2.0, dtype=np.float64),
                        random_small_pair(8, 40, 5), random_small_pair(16, 16, 6),
                        config1_pairs([-80], nt=160, dt=1.0 / 159)[0]], np.float32)
-    ref = oracle_batch(gs, oracle.Params(tol_res=1e-8, max_iter=2000000))
+    ref = oracle_batch(gs, oracle.Params(tol_res=1e-8, max_iter=2000000, ls_mode=ls))
     K = 2 * max(r.iters for r, _ in ref)
-    p = E.SolverParams(precision=E.F32, tol_res=0.0, max_iter=K, check_every=K)
-    log(f"f32 to the optimum, K={K}")
+    p = E.SolverParams(precision=E.F32, tol_res=0.0, max_iter=K, check_every=K, ls_mode=ls)
+    log(f"f32 to the optimum, K={K}, ls_mode={ls}")
     plan, pcal, pobs, desc = make_plan(gs, p)
     emd, phi, u, info, _ = _solve(plan, pcal, pobs)
     for k, (r, _) in enumerate(ref):
