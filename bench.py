@@ -29,7 +29,7 @@ BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi,
 # Bytes crossing the L2 boundary per sweep over the algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest; the traffic figure is null for any other source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "5f23819790f19526", "ratio": 1.174}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "281cca39bc7d463e", "ratio": 1.133}
 
 
 def sweep_source_digest():
@@ -194,6 +194,38 @@ def main():
                 "algo_bytes_per_launch": int(algo_bytes / max(sweeps, 1))}
 
     extra = {}
+    # the one-pass kernels around the solve, timed on their own: decompose (reads
+    # Pcal and Pobs, writes s: 12 B per cell at least; it makes two passes, 20 B) and
+    # the adjoint source (reads phi, writes psi: 8 B; two passes, 12 B); and a plain
+    # device copy of 1 GiB as the measured bandwidth ceiling
+    reps = 5
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    big = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev)
+    big2 = torch.empty_like(big)
+    big2.copy_(big)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        E.emd_decompose(plan, pcal, pobs, s_out=bufs["s"], mass_out=bufs["mass"])
+    ev[1].record(stream)
+    for _ in range(reps):
+        E.emd_adjoint_source(plan, bufs["phi"], pcal, pobs, bufs["mass"], psi_out=bufs["psi"])
+    ev[2].record(stream)
+    for _ in range(reps):
+        big2.copy_(big)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_dec = ev[0].elapsed_time(ev[1]) / reps
+    t_adj = ev[1].elapsed_time(ev[2]) / reps
+    copy_gbs = 2 * big.numel() * 4 / (ev[2].elapsed_time(ev[3]) / reps / 1e3) / 1e9
+    del big, big2
+    extra["one_pass_kernels"] = {
+        "decompose": {"ms": round(t_dec, 3), "GB/s_at_12B_per_cell": round(12 * cells / t_dec / 1e6, 1)},
+        "adjoint": {"ms": round(t_adj, 3), "GB/s_at_8B_per_cell": round(8 * cells / t_adj / 1e6, 1)}}
+    roofline["measured_copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"decompose {t_dec:.3f} ms, adjoint {t_adj:.3f} ms, 1 GiB copy {copy_gbs:.0f} GB/s")
+
     if not args.no_f64:
         # the plain FP64 solve: one gather per plan (its own launch sequence), to the
         # same stop rule, on a bounded sample of the workload's gathers
