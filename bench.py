@@ -189,7 +189,7 @@ def main():
         traffic = round(MEASURED_TRAFFIC["ratio"] * achieved, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_sweep<float>", "launches": int(sweeps),
+                "kernel": "k_sweep<float, false>", "launches": int(sweeps),
                 "avg_launch_us": round(sweep_ms * 1e3 / max(sweeps, 1), 2),
                 "algo_bytes_per_launch": int(algo_bytes / max(sweeps, 1))}
 

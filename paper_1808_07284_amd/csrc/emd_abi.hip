@@ -39,6 +39,7 @@ emd_status fail(emd_status st, const std::string& msg)
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kDefaultRows = 16;
+constexpr int kChains = 2;  // independent chains of sweep launches per captured chunk
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -66,7 +67,8 @@ struct emd_plan {
     // device memory
     GatherMeta* d_meta = nullptr;
     Tile* d_tiles = nullptr;      // every gather's tiles (auxiliary kernels, first chunk)
-    Tile* d_tiles_act = nullptr;  // the running gathers' tiles, rebuilt as gathers finish
+    Tile* d_tiles_act = nullptr;  // [kChains][act_cap] the running gathers' tiles, by chain
+    int64_t act_cap = 0;          // entries per chain in d_tiles_act
     void* d_fields = nullptr;  // one allocation: s, ux[2], ut[2], phi[2], R[2]
     double* d_part = nullptr;     // [2][slots][NPART]
     double* d_part_l1 = nullptr;  // [2][slots][NPART_L1] (l1 linesearch test)
@@ -236,6 +238,7 @@ emd_status build_tiles(emd_plan* plan)
     plan->nslots = slots;
     plan->padded_len = poff;
     plan->grid = (int)(tiles.size() / kWavesPerBlock);  // kXcd runs of whole blocks
+    plan->act_cap = 2 * (int64_t)tiles.size();
     if (realloc_tiles) {
         if (plan->d_tiles) (void)hipFree(plan->d_tiles);
         if (plan->d_tiles_act) (void)hipFree(plan->d_tiles_act);
@@ -246,7 +249,7 @@ emd_status build_tiles(emd_plan* plan)
         plan->d_part = nullptr;
         plan->d_part_l1 = nullptr;
         if (hipMalloc(&plan->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
-            hipMalloc(&plan->d_tiles_act, sizeof(Tile) * tiles.size()) != hipSuccess ||
+            hipMalloc(&plan->d_tiles_act, sizeof(Tile) * 2 * tiles.size() * kChains) != hipSuccess ||
             hipMalloc(&plan->d_part, sizeof(double) * NPART * 2 * slots) != hipSuccess ||
             hipMalloc(&plan->d_part_l1, sizeof(double) * NPART_L1 * 2 * slots) != hipSuccess)
             return fail(EMD_ERR_OUT_OF_MEMORY, "cannot allocate the tile table");
@@ -340,29 +343,107 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
     return a;
 }
 
-// Enqueue `count` (even) sweeps starting at parity 0.  Uses a captured graph of
-// sweeps_per_sync launches when count equals that chunk size.
+// The sweep launches of a solve.  The running gathers are split into up to kChains
+// groups of about equal cells, each with its own tile table (laid out over the XCDs
+// like the full table), and a captured chunk runs the groups as independent chains
+// of launches: while the last waves of one group's sweep drain, the other group's
+// next sweep fills the GPU.  A gather belongs to exactly one chain, so its sweeps
+// stay in order; the groups share nothing but the finished counter.
 template <typename T>
-emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int grid, int count, hipStream_t stream)
+struct Chains {
+    int n;
+    int grid[kChains];
+    SweepArgs<T> args[kChains];
+};
+
+// Split the selected gathers (largest first, each to the lighter group) and upload
+// the groups' tile tables.  Falls back to one chain over the full table when a
+// group's table would not fit its share of the buffer.
+template <typename T>
+emd_status build_chains(emd_plan* plan, const std::vector<char>& sel, const SweepArgs<T>& base,
+                        Chains<T>& ch, hipStream_t stream)
+{
+    std::memset(&ch, 0, sizeof(ch));  // the graph key compares these bytes
+    std::vector<int> order;
+    for (int g = 0; g < plan->ngather; ++g)
+        if (sel[g]) order.push_back(g);
+    auto cells = [&](int g) { return (int64_t)plan->desc[g].nr * plan->desc[g].nt; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells(x) > cells(y); });
+    const int nc = std::max(1, std::min((int)order.size(), kChains));
+    std::vector<std::vector<char>> part(nc, std::vector<char>(plan->ngather, 0));
+    int64_t load[kChains] = {};
+    for (int g : order) {
+        int k = 0;
+        for (int j = 1; j < nc; ++j)
+            if (load[j] < load[k]) k = j;
+        part[k][g] = 1;
+        load[k] += cells(g);
+    }
+    std::vector<std::vector<Tile>> tabs(nc);
+    for (int k = 0; k < nc; ++k) {
+        tabs[k] = layout_tiles(plan, part[k]);
+        if ((int64_t)tabs[k].size() > plan->act_cap) {
+            ch.n = 1;
+            ch.args[0] = base;
+            ch.args[0].tiles = plan->d_tiles;
+            ch.args[0].ntiles = plan->ntiles;
+            ch.grid[0] = plan->grid;
+            return EMD_SUCCESS;
+        }
+    }
+    ch.n = nc;
+    for (int k = 0; k < nc; ++k) {
+        Tile* dst = plan->d_tiles_act + (int64_t)k * plan->act_cap;
+        HIP_TRY(hipMemcpyAsync(dst, tabs[k].data(), sizeof(Tile) * tabs[k].size(), hipMemcpyHostToDevice, stream));
+        ch.args[k] = base;
+        ch.args[k].tiles = dst;
+        ch.args[k].ntiles = (int32_t)tabs[k].size();
+        ch.grid[k] = (int)(tabs[k].size() / kWavesPerBlock);
+    }
+    HIP_TRY(hipStreamSynchronize(stream));  // the host tables must outlive the copies
+    return EMD_SUCCESS;
+}
+
+// Enqueue `count` (even) sweeps starting at parity 0.  Uses a captured graph of
+// sweeps_per_sync launches per chain when count equals that chunk size.
+template <typename T>
+emd_status enqueue_sweeps(emd_plan* plan, const Chains<T>& ch, int count, hipStream_t stream)
 {
     const int chunk = plan->params.sweeps_per_sync;
     if (count == chunk) {
-        std::vector<unsigned char> key(sizeof(a) + sizeof(grid));
-        std::memcpy(key.data(), &a, sizeof(a));
-        std::memcpy(key.data() + sizeof(a), &grid, sizeof(grid));
+        std::vector<unsigned char> key(sizeof(ch));
+        std::memcpy(key.data(), &ch, sizeof(ch));
         if (!plan->graph || plan->graph_chunk != chunk || plan->graph_key != key) {
             destroy_graph(plan);
-            hipStream_t cs;
-            HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipStream_t cs[kChains] = {};
+            hipEvent_t fork = nullptr, join[kChains] = {};
             hipGraph_t g = nullptr;
-            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            hipError_t e = hipStreamCreateWithFlags(&cs[0], hipStreamNonBlocking);
+            for (int k = 1; k < ch.n && e == hipSuccess; ++k) {
+                e = hipStreamCreateWithFlags(&cs[k], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+            }
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, grid, cs);
-                e = hipStreamEndCapture(cs, &g);
+                // fork the other chains off the capture stream, join them at the end
+                if (ch.n > 1) (void)hipEventRecord(fork, cs[0]);
+                for (int k = 1; k < ch.n; ++k) (void)hipStreamWaitEvent(cs[k], fork, 0);
+                for (int n = 0; n < count; ++n)
+                    for (int k = 0; k < ch.n; ++k) launch_sweep<T>(ch.args[k], n & 1, ch.grid[k], cs[k]);
+                for (int k = 1; k < ch.n; ++k) {
+                    (void)hipEventRecord(join[k], cs[k]);
+                    (void)hipStreamWaitEvent(cs[0], join[k], 0);
+                }
+                e = hipStreamEndCapture(cs[0], &g);
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);
-            (void)hipStreamDestroy(cs);
+            if (fork) (void)hipEventDestroy(fork);
+            for (int k = 0; k < kChains; ++k) {
+                if (join[k]) (void)hipEventDestroy(join[k]);
+                if (cs[k]) (void)hipStreamDestroy(cs[k]);
+            }
             if (e != hipSuccess) {
                 plan->graph = nullptr;
                 return fail(EMD_ERR_HIP, std::string("graph capture of the sweeps failed: ") +
@@ -374,7 +455,8 @@ emd_status enqueue_sweeps(emd_plan* plan, const SweepArgs<T>& a, int grid, int c
         HIP_TRY(hipGraphLaunch(plan->graph, stream));
         return EMD_SUCCESS;
     }
-    for (int n = 0; n < count; ++n) launch_sweep<T>(a, n & 1, grid, stream);
+    for (int n = 0; n < count; ++n)
+        for (int k = 0; k < ch.n; ++k) launch_sweep<T>(ch.args[k], n & 1, ch.grid[k], stream);
     HIP_TRY(hipGetLastError());
     return EMD_SUCCESS;
 }
@@ -400,23 +482,26 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     HIP_TRY(hipGetLastError());
 
     const int ls_mode = replay ? LS_REPLAY : plan->params.ls_mode;
-    SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
-    int grid = plan->grid;
+    const SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
+    Chains<T> ch;
+    std::memset(&ch, 0, sizeof(ch));
+    std::vector<char> sel(plan->ngather, 1);
+    emd_status cst = build_chains<T>(plan, sel, sa, ch, stream);
+    if (cst != EMD_SUCCESS) return cst;
     const int chunk = plan->params.sweeps_per_sync;
     // a gather needs iters + 1 sweeps, the last one applying the final dual step;
     // the l1 test may add an evaluation sweep per NL1 failed backtracking trials
     const int64_t evals = ls_mode == LS_L1 ? plan->params.max_ls_trials / NL1 + 1 : 0;
     const int64_t max_sweeps = round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
     int64_t sweeps = 0;
-    // Finished gathers leave the sweep's tile table: once the running gathers hold at
-    // most 7/8 of the table's cells, the table is rebuilt from them alone and spread
+    // Finished gathers leave the sweep's tile tables: once the running gathers hold at
+    // most 7/8 of the tables' cells, the chains are rebuilt from them alone and spread
     // over the XCDs again.  Tiles keep their shape and partial-sum slots, so every
     // decision, and hence every result, is bitwise the same as with the full table.
     int64_t table_cells = plan->cells;
     int32_t known_out = 0;  // finished gathers seen at the last status read
     int64_t rebuilds = 0;
     std::vector<GState> gs(plan->ngather);
-    std::vector<char> sel(plan->ngather);
     HIP_TRY(hipEventRecord(plan->ev0, stream));
     for (;;) {
         // the finished count before any sweep (gathers with nothing to solve)
@@ -442,21 +527,14 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
             }
             known_out = out;
             if (live > 0 && live * 8 <= table_cells * 7) {
-                const std::vector<Tile> tiles = layout_tiles(plan, sel);
-                if ((int64_t)tiles.size() <= plan->ntiles) {
-                    HIP_TRY(hipMemcpyAsync(plan->d_tiles_act, tiles.data(), sizeof(Tile) * tiles.size(),
-                                           hipMemcpyHostToDevice, stream));
-                    HIP_TRY(hipStreamSynchronize(stream));
-                    sa.tiles = plan->d_tiles_act;
-                    sa.ntiles = (int32_t)tiles.size();
-                    grid = (int)(tiles.size() / kWavesPerBlock);
-                    table_cells = live;
-                    ++rebuilds;
-                }
+                cst = build_chains<T>(plan, sel, sa, ch, stream);
+                if (cst != EMD_SUCCESS) return cst;
+                table_cells = live;
+                ++rebuilds;
             }
         }
         const int count = (int)std::min<int64_t>(chunk, max_sweeps - sweeps);
-        emd_status st = enqueue_sweeps<T>(plan, sa, grid, count, stream);
+        emd_status st = enqueue_sweeps<T>(plan, ch, count, stream);
         if (st != EMD_SUCCESS) return st;
         sweeps += count;
     }
@@ -592,7 +670,8 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
     }
     plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
                             (int64_t)sizeof(double) * (NPART + NPART_L1) * 2 * plan->nslots +
-                            (int64_t)sizeof(Tile) * 2 * plan->ntiles + (int64_t)sizeof(GatherMeta) * ngather;
+                            (int64_t)sizeof(Tile) * (1 + 2 * kChains) * plan->ntiles +
+                            (int64_t)sizeof(GatherMeta) * ngather;
     *out = plan;
     return EMD_SUCCESS;
 }
