@@ -102,7 +102,8 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--tol", type=float, default=1e-5, help="relative residual stop rule")
     ap.add_argument("--max-iter", type=int, default=100000)
-    ap.add_argument("--rows", type=int, default=0, help="rows per tile (0: plan default)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per tile for every gather (0: autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile height")
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--f64-gathers", type=int, default=2,
                     help="gathers of the workload solved by the plain FP64 path (bounded sample)")
@@ -140,8 +141,17 @@ def main():
     pobs = torch.from_numpy(pobs_h).to(dev)
     params = E.SolverParams(precision=E.F32, tol_res=args.tol, max_iter=args.max_iter)
     plan = E.Plan(desc, len(pcal_h), params)
+    heights = None
     if args.rows:
         plan.set_tiling(args.rows)
+    elif not args.no_autotune:
+        # tile heights per size bucket, picked by the library's autotuner (untimed setup)
+        s0, _ = E.emd_decompose(plan, pcal, pobs)
+        t_at = time.perf_counter()
+        rows = plan.autotune(s0)
+        del s0
+        heights = {str(h): rows.count(h) for h in sorted(set(rows))}
+        log(f"autotuned tile heights {heights} in {time.perf_counter() - t_at:.1f} s")
     bufs = {"s": plan.empty(), "phi": plan.empty(), "psi": plan.empty(),
             "mass": torch.empty(len(gathers), 3, dtype=torch.float64, device=dev),
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
@@ -271,7 +281,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wdesc, "gathers": len(gathers), "cells": cells,
                       "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
-                      "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max())},
+                      "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
+                      "tile_rows": heights if heights else (args.rows or 16)},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))

@@ -156,9 +156,29 @@ emd_status emd_plan_destroy(emd_plan* plan);
 /* Replace the solver parameters of an existing plan (precision must not change). */
 emd_status emd_plan_set_params(emd_plan* plan, const emd_params* p);
 
-/* Choose the tile height (receiver rows per wavefront tile, 1..1024) used by the
- * solver sweeps; 0 restores the plan's default.  Used by the autotuner. */
+/* Choose the tile height (receiver rows per wavefront tile, 1..1024) of every
+ * gather's solver sweeps; 0 restores the default (16).  The fields a solve returns
+ * do not depend on the tiling for a fixed step schedule; the linesearch inner
+ * products are summed per tile, so free-running results may differ in the last
+ * bits between tilings (each tiling is bitwise reproducible).  Synchronises the
+ * device. */
 emd_status emd_plan_set_tiling(emd_plan* plan, int32_t rows_per_tile);
+
+/* Per-gather tile heights: h_rows is a host array of ngather values in [1, 1024]
+ * (set) or receives them (get).  set synchronises the device. */
+emd_status emd_plan_set_gather_tiling(emd_plan* plan, const int32_t* h_rows);
+emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows);
+
+/* Tile-height autotuner.  Puts the gathers in 3 x 3 size buckets (tertiles of nt
+ * and of nr over the batch) and, bucket by bucket (largest first), tries heights
+ * 8, 12, 16, 24 and 32 for that bucket, timing a fixed-step solve of `sweeps`
+ * sweeps (even, 4..4096; 0 = 48) of the whole batch from the source s (as given to
+ * emd_pdhg_solve) in the production launch configuration, and keeps a height when
+ * it is faster by more than 0.3 %.  The chosen heights stay in the plan (read them
+ * with emd_plan_get_gather_tiling to reuse them).  The plan's parameters are left
+ * unchanged; its workspace is overwritten; synchronises the device.  Timing-based,
+ * so the choice can differ from run to run. */
+emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipStream_t stream);
 
 /* Fill *out with the plan's sizes and the counters of its last solve. */
 emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out);

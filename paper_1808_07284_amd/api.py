@@ -114,6 +114,26 @@ class Plan:
         with torch.cuda.device(self.device):
             L.check(L.load().emd_plan_set_tiling(self.handle, int(rows_per_tile)))
 
+    def set_gather_tiling(self, rows):
+        """Tile height (receiver rows per wavefront tile) of each gather."""
+        arr = (C.c_int32 * self.ngather)(*[int(r) for r in rows])
+        with torch.cuda.device(self.device):
+            L.check(L.load().emd_plan_set_gather_tiling(self.handle, arr))
+
+    def gather_tiling(self) -> list:
+        arr = (C.c_int32 * self.ngather)()
+        L.check(L.load().emd_plan_get_gather_tiling(self.handle, arr))
+        return list(arr)
+
+    def autotune(self, s, sweeps: int = 0) -> list:
+        """Pick tile heights per size bucket by timing short fixed-step solves from the
+        source s (the workspace is overwritten; the parameters are kept).  Returns the
+        chosen per-gather heights."""
+        self._check(s, "s")
+        with torch.cuda.device(self.device):
+            L.check(L.load().emd_plan_autotune(self.handle, _ptr(s), int(sweeps), _stream(self.device)))
+        return self.gather_tiling()
+
     def query(self) -> dict:
         s = L.PlanStats()
         L.check(L.load().emd_plan_query(self.handle, C.byref(s)))

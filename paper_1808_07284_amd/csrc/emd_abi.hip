@@ -53,7 +53,8 @@ struct emd_plan {
     std::vector<emd_gather_desc> desc;
     size_t elem = 4;          // bytes per field element
     int vec = 4;              // elements per lane vector
-    int rows = kDefaultRows;  // receiver rows per tile
+    int rows = kDefaultRows;  // receiver rows per tile (the default for every gather)
+    std::vector<int> grows;   // receiver rows per tile, per gather
     int64_t padded_len = 0;
     int32_t ntiles = 0;       // entries of the tile table (including empty padding)
     int32_t nslots = 0;       // real tiles = partial-sum slots
@@ -162,7 +163,7 @@ std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& se
     for (int g = 0; g < plan->ngather; ++g) {
         if (!sel[g]) continue;
         for (int st = 0; st < nst[g]; ++st) {
-            const int64_t c = (int64_t)std::min(plan->rows, meta[g].nr - st * plan->rows) * meta[g].nt;
+            const int64_t c = (int64_t)std::min(meta[g].rows, meta[g].nr - st * meta[g].rows) * meta[g].nt;
             strips.push_back(Strip{g, st, c});
             total += c;
         }
@@ -179,7 +180,7 @@ std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& se
         for (size_t s = s0; s < s1; ++s) {
             const int g = strips[s].g, st = strips[s].st;
             for (int tt = 0; tt < ntt[g]; ++tt)
-                runs[x].push_back(Tile{g, st * plan->rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
+                runs[x].push_back(Tile{g, st * meta[g].rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
         }
         s0 = s1;
     }
@@ -221,10 +222,10 @@ emd_status build_tiles(emd_plan* plan)
         m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
                                              : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
         ntt[g] = (d.nt + span - 1) / span;
-        nst[g] = (d.nr + plan->rows - 1) / plan->rows;
+        m.rows = plan->grows[g];
+        nst[g] = (d.nr + m.rows - 1) / m.rows;
         m.tile_base = slots;
         m.ntiles = ntt[g] * nst[g];
-        m.pad0 = 0;
         slots += m.ntiles;
         poff += round_up((int64_t)d.nr * m.ld, 64);
     }
@@ -296,7 +297,6 @@ AuxArgs<T> aux_args(emd_plan* plan)
     a.meta = plan->d_meta;
     a.tiles = plan->d_tiles;
     a.ntiles = plan->ntiles;
-    a.rows = plan->rows;
     a.ngather = plan->ngather;
     a.mass_mode = plan->params.mass_mode;
     a.mass_tol = plan->params.mass_tol;
@@ -325,7 +325,6 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
     a.meta = plan->d_meta;
     a.tiles = plan->d_tiles;
     a.ntiles = plan->ntiles;
-    a.rows = plan->rows;
     a.s = field<T>(plan, 0);
     for (int b = 0; b < 2; ++b) {
         a.ux[b] = field<T>(plan, 1 + b);
@@ -638,6 +637,7 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
     plan->batch_len = batch_len;
     plan->params = *p;
     plan->desc.assign(h_desc, h_desc + ngather);
+    plan->grows.assign(ngather, kDefaultRows);
     plan->elem = p->precision == EMD_F64 ? 8 : 4;
     plan->vec = p->precision == EMD_F64 ? 2 : 4;
     for (auto& d : plan->desc) plan->cells += (int64_t)d.nr * d.nt;
@@ -721,7 +721,131 @@ emd_status emd_plan_set_tiling(emd_plan* plan, int32_t rows_per_tile)
     if (st != EMD_SUCCESS) return st;
     HIP_TRY(hipDeviceSynchronize());
     plan->rows = rows_per_tile == 0 ? kDefaultRows : rows_per_tile;
+    plan->grows.assign(plan->ngather, plan->rows);
     return build_tiles(plan);
+}
+
+emd_status emd_plan_set_gather_tiling(emd_plan* plan, const int32_t* h_rows)
+{
+    g_last_error.clear();
+    if (!plan || !h_rows) return fail(EMD_ERR_NULL_POINTER, "plan or h_rows is NULL");
+    for (int g = 0; g < plan->ngather; ++g)
+        if (h_rows[g] < 1 || h_rows[g] > 1024)
+            return fail(EMD_ERR_INVALID_ARGUMENT, "rows per tile must lie in [1, 1024] (gather " +
+                                                      std::to_string(g) + ")");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    plan->grows.assign(h_rows, h_rows + plan->ngather);
+    return build_tiles(plan);
+}
+
+emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows)
+{
+    g_last_error.clear();
+    if (!plan || !h_rows) return fail(EMD_ERR_NULL_POINTER, "plan or h_rows is NULL");
+    for (int g = 0; g < plan->ngather; ++g) h_rows[g] = plan->grows[g];
+    return EMD_SUCCESS;
+}
+
+// Tile-height autotuner.  Gathers fall into 3 x 3 size buckets (tertiles of nt and
+// of nr over the batch); bucket by bucket, largest first, each candidate height is
+// tried for that bucket's gathers with the others fixed, keeping it when a short
+// fixed-step solve of the whole batch (the production launch configuration: the
+// captured chunk with its chains) runs faster by more than the timing noise.
+emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan || !s) return fail(EMD_ERR_NULL_POINTER, "plan or s is NULL");
+    if (sweeps == 0) sweeps = 48;
+    if (sweeps < 4 || sweeps > 4096 || (sweeps & 1))
+        return fail(EMD_ERR_INVALID_ARGUMENT, "sweeps must be even and lie in [4, 4096]");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    const emd_params saved = plan->params;
+    const std::vector<int> saved_rows = plan->grows;
+    plan->params.ls_mode = EMD_LS_FIXED;
+    plan->params.max_iter = sweeps - 2;  // max_iter + 2 sweeps: one captured chunk
+    plan->params.check_every = sweeps - 2;
+    plan->params.tol_res = 0.0;
+    plan->params.sweeps_per_sync = sweeps;
+    auto restore = [&](emd_status code) {
+        plan->params = saved;
+        if (code != EMD_SUCCESS) {
+            const std::string msg = g_last_error;
+            plan->grows = saved_rows;
+            (void)build_tiles(plan);
+            g_last_error = msg;
+        }
+        return code;
+    };
+    // one untimed solve captures the graph of this tiling, the second is timed
+    auto timed = [&](float& ms) -> emd_status {
+        for (int r = 0; r < 2; ++r) {
+            const emd_status e =
+                plan->params.precision == EMD_F32
+                    ? solve_impl<float>(plan, s, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, stream)
+                    : solve_impl<double>(plan, s, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, stream);
+            if (e != EMD_SUCCESS) return e;
+        }
+        HIP_TRY(hipEventElapsedTime(&ms, plan->ev0, plan->ev1));
+        return EMD_SUCCESS;
+    };
+    const int n = plan->ngather;
+    std::vector<int> nts(n), nrs(n);
+    for (int g = 0; g < n; ++g) {
+        nts[g] = plan->desc[g].nt;
+        nrs[g] = plan->desc[g].nr;
+    }
+    std::vector<int> snt = nts, snr = nrs;
+    std::sort(snt.begin(), snt.end());
+    std::sort(snr.begin(), snr.end());
+    auto bin = [&](const std::vector<int>& sorted, int v) {
+        return (v >= sorted[n / 3] ? 1 : 0) + (v >= sorted[(2 * n) / 3] ? 1 : 0);
+    };
+    std::vector<int> bucket(n);
+    int64_t bcells[9] = {};
+    for (int g = 0; g < n; ++g) {
+        bucket[g] = 3 * bin(snt, nts[g]) + bin(snr, nrs[g]);
+        bcells[bucket[g]] += (int64_t)nts[g] * nrs[g];
+    }
+    int order[9];
+    for (int b = 0; b < 9; ++b) order[b] = b;
+    std::stable_sort(order, order + 9, [&](int x, int y) { return bcells[x] > bcells[y]; });
+
+    std::vector<int> best_rows = plan->grows;
+    st = build_tiles(plan);
+    if (st != EMD_SUCCESS) return restore(st);
+    float best = 0.f;
+    st = timed(best);
+    if (st != EMD_SUCCESS) return restore(st);
+    static const int kCand[] = {8, 12, 16, 24, 32};
+    for (int bi = 0; bi < 9; ++bi) {
+        const int b = order[bi];
+        if (bcells[b] == 0) continue;
+        int cur = 0;
+        for (int g = 0; g < n; ++g)
+            if (bucket[g] == b) cur = best_rows[g];
+        for (int c : kCand) {
+            if (c == cur) continue;
+            std::vector<int> trial = best_rows;
+            for (int g = 0; g < n; ++g)
+                if (bucket[g] == b) trial[g] = c;
+            plan->grows = trial;
+            st = build_tiles(plan);
+            if (st != EMD_SUCCESS) return restore(st);
+            float ms = 0.f;
+            st = timed(ms);
+            if (st != EMD_SUCCESS) return restore(st);
+            if (ms < best * 0.997f) {
+                best = ms;
+                best_rows = trial;
+            }
+        }
+    }
+    plan->grows = best_rows;
+    st = build_tiles(plan);
+    return restore(st);
 }
 
 emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out)

@@ -35,7 +35,7 @@ __device__ __forceinline__ TileView tile_view(const AuxArgs<T>& a, GatherMeta& g
     gm = a.meta[v.g];
     v.lane = threadIdx.x & (WAVE - 1);
     v.r0 = tl.r0;
-    v.rend = min(tl.r0 + a.rows, gm.nr);
+    v.rend = min(tl.r0 + gm.rows, gm.nr);
     v.j0 = tl.c0 - V + V * v.lane;
     v.active = (v.lane >= 1) && (v.lane <= OUT_LANES) && (v.j0 >= 0) && (v.j0 < gm.nt);
     return v;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_copy_out(AuxArgs<T> a)
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             if (tv.j0 + k >= gm.nt) break;
-            a.phi_user_out[ur + k] = zero ? T(0) : ph[k];
+            if (a.phi_user_out) a.phi_user_out[ur + k] = zero ? T(0) : ph[k];
             if (a.u_user_out) {
                 a.u_user_out[ur + k] = zero ? T(0) : ux[k];
                 a.u_user_out[a.batch_len + ur + k] = zero ? T(0) : ut[k];

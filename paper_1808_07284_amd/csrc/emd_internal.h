@@ -51,7 +51,8 @@ constexpr int HALO_LANE_R = OUT_LANES + 1;
 
 struct GatherMeta {
     int32_t nr, nt, ld, ntiles;  // grid, padded pitch, sweep tiles of the gather
-    int32_t tile_base, pad0;     // first tile in the tile table
+    int32_t tile_base;           // first partial-sum slot (tiles own consecutive slots)
+    int32_t rows;                // receiver rows per tile (one strip)
     int64_t poff;                // element offset in the padded workspace fields
     int64_t uoff;                // element offset in the caller's batch buffers
     double dx, dt;               // EMD grid spacings

@@ -12,7 +12,7 @@ template <typename T>
 struct SweepArgs {
     const GatherMeta* meta;
     const Tile* tiles;
-    int32_t ntiles, rows;  // tiles in the table, receiver rows per tile
+    int32_t ntiles, pad0;  // tiles in the table
     const T* s;            // padded source
     T* ux[2];
     T* ut[2];
@@ -30,7 +30,7 @@ template <typename T>
 struct AuxArgs {
     const GatherMeta* meta;
     const Tile* tiles;
-    int32_t ntiles, rows, ngather, mass_mode;
+    int32_t ntiles, pad0, ngather, mass_mode;
     double mass_tol;
     // caller's buffers (dense [nr][nt] at meta.uoff)
     const T* pcal;

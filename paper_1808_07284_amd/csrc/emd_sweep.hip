@@ -877,9 +877,9 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     c.ld = gm.ld;
     const int nt = gm.nt;
     c.r0 = tl.r0;
-    c.rend = min(tl.r0 + a.rows, gm.nr);
+    c.rend = min(tl.r0 + gm.rows, gm.nr);
     c.ibeg = max(tl.r0 - 2, 0);
-    c.ilast = min(tl.r0 + a.rows, gm.nr);  // == nr: the virtual row closes the last strip
+    c.ilast = min(tl.r0 + gm.rows, gm.nr);  // == nr: the virtual row closes the last strip
     const int j0 = tl.c0 - V + V * lane;
     const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
     c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     // need no time-boundary masks
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
     // odd strips march up
-    const bool up = ((tl.r0 / a.rows) & 1) != 0;
+    const bool up = ((tl.r0 / gm.rows) & 1) != 0;
     if (edge) {
         if (up) sweep_tile<T, true, true, ABS>(a, tl, gm, parity, pb);
         else sweep_tile<T, true, false, ABS>(a, tl, gm, parity, pb);

@@ -305,9 +305,15 @@ def test_replay_fields_are_independent_of_tiling():
         alpha[k] = 1.0 / np.sqrt(1e5 * lam) * 1.3 ** np.minimum(np.arange(K), 20)
     p = E.SolverParams(precision=E.F32, max_iter=K, tol_res=0.0, check_every=K)
     outs = []
-    for rows in (1, 3, 16, 64):
+    # uniform heights, then a different height per gather
+    for rows in (1, 3, 16, 64, [5, 2, 7, 1, 3, 12]):
         log(f"tiling rows={rows}")
-        plan, pcal, pobs, desc = make_plan(gs, p, rows=rows)
+        if isinstance(rows, list):
+            plan, pcal, pobs, desc = make_plan(gs, p)
+            plan.set_gather_tiling(rows)
+            assert plan.gather_tiling() == rows
+        else:
+            plan, pcal, pobs, desc = make_plan(gs, p, rows=rows)
         s, mass = E.emd_decompose(plan, pcal, pobs)
         u = plan.empty(2)
         emd, phi, u, info = E.emd_pdhg_solve_replay(plan, s, torch.from_numpy(alpha).cuda(), u=u)
@@ -317,6 +323,38 @@ def test_replay_fields_are_independent_of_tiling():
     for o in outs[1:]:
         np.testing.assert_array_equal(o[0], outs[0][0])
         np.testing.assert_array_equal(o[1], outs[0][1])
+
+
+def test_autotuned_tiling_is_valid_and_reusable():
+    # the autotuner picks a height per size bucket; a plan given the same heights
+    # reproduces a solve bitwise, and the result agrees with the default tiling
+    from synth import config3_batch
+    gs = config3_batch()[:12]
+    p = E.SolverParams(precision=E.F32, max_iter=300, tol_res=0.0, check_every=300)
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    rows = plan.autotune(s, sweeps=8)
+    log(f"  autotuned heights {rows}")
+    assert set(rows) <= {8, 12, 16, 24, 32}
+    nts = np.array([g.nt for g in gs])
+    nrs = np.array([g.nr for g in gs])
+    tert = lambda v: (v >= np.sort(v)[len(v) // 3]).astype(int) + (v >= np.sort(v)[2 * len(v) // 3])
+    bucket = 3 * tert(nts) + tert(nrs)
+    for b in set(bucket.tolist()):
+        assert len({rows[k] for k in np.flatnonzero(bucket == b)}) == 1
+    assert plan.params.ls_mode == E.LS_L2
+    e1, phi1, _, i1 = E.emd_pdhg_solve(plan, s, mass=mass)
+    plan2, _, _, _ = make_plan(gs, p)
+    plan2.set_gather_tiling(rows)
+    e2, phi2, _, i2 = E.emd_pdhg_solve(plan2, s, mass=mass)
+    plan3, _, _, _ = make_plan(gs, p)
+    e3, _, _, _ = E.emd_pdhg_solve(plan3, s, mass=mass)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(e1.cpu().numpy(), e2.cpu().numpy())
+    np.testing.assert_array_equal(phi1.cpu().numpy(), phi2.cpu().numpy())
+    np.testing.assert_allclose(e1.cpu().numpy(), e3.cpu().numpy(), rtol=1e-5)
+    for pl in (plan, plan2, plan3):
+        pl.close()
 
 
 def test_repeat_solves_are_bitwise_deterministic():
