@@ -82,6 +82,8 @@ def _load():
         lib.oracle_solve.restype = C.c_int
         lib.oracle_adjoint.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp,
                                        dp, C.c_int, C.c_double, dp]
+        lib.oracle_lsd.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        lib.oracle_lsd.restype = C.c_double
         lib.oracle_misfit.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp,
                                       C.c_int, C.POINTER(_Params), dp, dp, dp, dp,
                                       C.POINTER(_Info)]
@@ -209,6 +211,16 @@ def solve(s, dx, dt, params: Params | None = None, u0=None, phi0=None,
     return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
                        info.emd, info.transport,
                        tr[:info.iters].copy() if trace else None)
+
+
+def lsd(pcal, pobs, dx, dt):
+    """Least-squares misfit 1/2 dx dt sum (Pcal - Pobs)^2 and its gradient dx dt (Pcal - Pobs)."""
+    pcal = _f64(pcal)
+    pobs = _f64(pobs)
+    nr, nt = pcal.shape
+    grad = np.zeros_like(pcal)
+    f = _load().oracle_lsd(nr, nt, dx, dt, _p(pcal), _p(pobs), _p(grad))
+    return f, grad
 
 
 def adjoint(phi, pcal, pobs, mass, dx, dt, mass_mode=MASS_BALANCE, gbar=1.0):

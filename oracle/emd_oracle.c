@@ -478,3 +478,26 @@ int oracle_misfit(int nr, int nt, double dx, double dt, const double* pcal,
     free(s);
     return st;
 }
+
+/* ---------------------------------------------------------- least squares */
+
+/* The conventional least-squares misfit the paper compares the EMD with (Section
+ * 2.1), f = 1/2 * integral (Pcal - Pobs)^2, as the cell sum
+ *   f = 1/2 dx dt sum (Pcal - Pobs)^2,
+ * and its gradient with respect to Pcal (the adjoint source of Section 2.3, Pcal -
+ * Pobs, times the cell measure as for the EMD's adjoint source),
+ *   grad = dx dt (Pcal - Pobs)            (grad may be NULL).
+ * Returns f. */
+double oracle_lsd(int nr, int nt, double dx, double dt, const double* pcal,
+                  const double* pobs, double* grad)
+{
+    int64_t n = (int64_t)nr * nt;
+    double cm = oracle_cell_measure(nr, nt, dx, dt);
+    double sum = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+        double d = pcal[c] - pobs[c];
+        sum += d * d;
+        if (grad) grad[c] = cm * d;
+    }
+    return 0.5 * cm * sum;
+}
