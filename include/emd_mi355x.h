@@ -235,6 +235,16 @@ emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal,
                               const void* pobs, const double* d_mass, const double* d_gbar,
                               void* psi_out, hipStream_t stream);
 
+/* The conventional least-squares misfit the paper compares the EMD with (Section
+ * 2.1) and its adjoint source (Section 2.3), per gather:
+ *   d_value[g] = 1/2 dx dt sum (Pcal - Pobs)^2      (FP64 sums in a fixed order),
+ *   psi_out    = gbar dx dt (Pcal - Pobs)           (the exact gradient; optional).
+ * pcal, pobs, psi_out: batch buffers of the plan's precision (psi_out NULL: value
+ * only; it must not alias pcal or pobs); d_gbar: device double[ngather] upstream
+ * gradients or NULL (= 1); d_value: device double[ngather].  Never synchronises. */
+emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, const double* d_gbar,
+                          double* d_value, void* psi_out, hipStream_t stream);
+
 /* Human-readable name of a call status. */
 const char* emd_status_string(emd_status status);
 

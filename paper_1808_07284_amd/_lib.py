@@ -27,7 +27,7 @@ F32, F64 = 0, 1
 EXPORTED = ["emd_params_default", "emd_plan_create", "emd_plan_destroy", "emd_plan_set_params",
             "emd_plan_set_tiling", "emd_plan_set_gather_tiling", "emd_plan_get_gather_tiling",
             "emd_plan_autotune", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
-            "emd_pdhg_solve_replay", "emd_adjoint_source", "emd_status_string",
+            "emd_pdhg_solve_replay", "emd_adjoint_source", "emd_lsd_misfit", "emd_status_string",
             "emd_last_error"]
 
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.emd_pdhg_solve.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
     lib.emd_pdhg_solve_replay.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int32, vp, vp, vp]
     lib.emd_adjoint_source.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.emd_lsd_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("emd_status_string", "emd_last_error"):
             getattr(lib, name).restype = st

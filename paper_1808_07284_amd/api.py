@@ -220,6 +220,24 @@ def emd_adjoint_source(plan: Plan, phi, pcal=None, pobs=None, mass=None, gbar=No
     return psi_out
 
 
+def lsd_misfit(plan: Plan, pcal, pobs, gbar=None, value_out=None, psi_out=None, with_adjoint=True):
+    """Least-squares misfit 1/2 dx dt sum (Pcal - Pobs)^2 per gather (Section 2.1) and its
+    adjoint source gbar dx dt (Pcal - Pobs) (Section 2.3).  Returns (value [ngather] float64,
+    psi or None)."""
+    if with_adjoint and psi_out is None:
+        psi_out = plan.empty()
+    for t, n in ((pcal, "pcal"), (pobs, "pobs"), (psi_out, "psi_out")):
+        plan._check(t, n)
+    value_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
+                 if value_out is None else value_out)
+    if gbar is not None:
+        gbar = gbar.to(device=plan.device, dtype=torch.float64).contiguous()
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_lsd_misfit(plan.handle, _ptr(pcal), _ptr(pobs), _ptr(gbar), _ptr(value_out),
+                                        _ptr(psi_out), _stream(plan.device)))
+    return value_out, psi_out
+
+
 def info_numpy(info: torch.Tensor) -> np.ndarray:
     """Per-gather emd_solve_info records as a numpy structured array."""
     return np.frombuffer(info.cpu().numpy().tobytes(), dtype=INFO_DTYPE)

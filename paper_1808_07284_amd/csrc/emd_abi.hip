@@ -972,6 +972,37 @@ emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal,
     return EMD_SUCCESS;
 }
 
+emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, const double* d_gbar,
+                          double* d_value, void* psi_out, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!pcal || !pobs || !d_value) return fail(EMD_ERR_NULL_POINTER, "pcal, pobs and d_value are required");
+    if (psi_out && (psi_out == pcal || psi_out == pobs))
+        return fail(EMD_ERR_INVALID_ARGUMENT, "psi_out aliases an input");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    if (plan->params.precision == EMD_F32) {
+        AuxArgs<float> a = aux_args<float>(plan);
+        a.pcal = static_cast<const float*>(pcal);
+        a.pobs = static_cast<const float*>(pobs);
+        a.gbar = d_gbar;
+        a.emd_out = d_value;
+        a.psi_out = static_cast<float*>(psi_out);
+        launch_lsd<float>(a, plan->grid, stream);
+    } else {
+        AuxArgs<double> a = aux_args<double>(plan);
+        a.pcal = static_cast<const double*>(pcal);
+        a.pobs = static_cast<const double*>(pobs);
+        a.gbar = d_gbar;
+        a.emd_out = d_value;
+        a.psi_out = static_cast<double*>(psi_out);
+        launch_lsd<double>(a, plan->grid, stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
 const char* emd_status_string(emd_status status)
 {
     switch (status) {

@@ -373,7 +373,55 @@ __global__ __launch_bounds__(256) void k_adj_apply(AuxArgs<T> a)
     }
 }
 
+// ------------------------------------------------------------------ least squares
+
+// psi = gbar dx dt (Pcal - Pobs) (optional); partial: sum (Pcal - Pobs)^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_lsd_apply(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok) return;
+    double acc[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    if (tv.active) {
+        const double scale = gm.cm * (a.gbar ? a.gbar[tv.g] : 1.0);
+        for (int i = tv.r0; i < tv.rend; ++i) {
+            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (tv.j0 + k >= gm.nt) break;
+                const double d = double(a.pcal[ur + k]) - double(a.pobs[ur + k]);
+                acc[0] = fma(d, d, acc[0]);
+                if (a.psi_out) a.psi_out[ur + k] = T(scale * d);
+            }
+        }
+    }
+    write_record(a.part, tv.slot, acc);
+}
+
+// value[g] = 1/2 dx dt sum (Pcal - Pobs)^2
+template <typename T>
+__global__ __launch_bounds__(64) void k_lsd_value(AuxArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const GatherMeta gm = a.meta[g];
+    double q[NPART];
+    reduce_records(a.part + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
+    if (threadIdx.x == 0) a.emd_out[g] = 0.5 * gm.cm * q[0];
+}
+
 }  // namespace
+
+template <typename T>
+void launch_lsd(const AuxArgs<T>& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_lsd_apply<T>, dim3(grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_lsd_value<T>, dim3(a.ngather), dim3(64), 0, stream, a);
+}
 
 template <typename T>
 void launch_copy_in(const AuxArgs<T>& a, int warm, int grid, hipStream_t stream)
@@ -426,7 +474,8 @@ void launch_zero_counter(int32_t* counter, hipStream_t stream)
     template void launch_copy_out<T>(const AuxArgs<T>&, int, hipStream_t);          \
     template void launch_finalize<T>(const AuxArgs<T>&, hipStream_t);               \
     template void launch_decompose<T>(const AuxArgs<T>&, int, hipStream_t);         \
-    template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);
+    template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);           \
+    template void launch_lsd<T>(const AuxArgs<T>&, int, hipStream_t);
 EMD_INST(float)
 EMD_INST(double)
 #undef EMD_INST

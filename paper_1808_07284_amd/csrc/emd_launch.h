@@ -71,6 +71,7 @@ template <typename T> void launch_copy_out(const AuxArgs<T>& a, int grid, hipStr
 template <typename T> void launch_finalize(const AuxArgs<T>& a, hipStream_t stream);
 template <typename T> void launch_decompose(const AuxArgs<T>& a, int grid, hipStream_t stream);
 template <typename T> void launch_adjoint(const AuxArgs<T>& a, int grid, hipStream_t stream);
+template <typename T> void launch_lsd(const AuxArgs<T>& a, int grid, hipStream_t stream);
 void launch_zero_counter(int32_t* counter, hipStream_t stream);
 
 }  // namespace emd

@@ -119,6 +119,47 @@ def test_shift_study_against_closed_form():
     plan.close()
 
 
+def _turns_in_span(x, ref, frac=0.01):
+    """Turning points of x over the span where |ref| exceeds frac of its peak."""
+    x = np.asarray(x, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    idx = np.flatnonzero(np.abs(ref) > frac * np.abs(ref).max())
+    d = np.diff(x[idx[0]:idx[-1] + 1])
+    d = d[d != 0]
+    return int(np.count_nonzero(np.diff(np.sign(d))))
+
+
+def test_paper_section_3_1_comparison_at_8hz():
+    # Section 3.1 at the paper's 8 Hz: the least-squares misfit skips cycles (local
+    # minima beside zero shift, at +-113.7 ms), the EMD has a single minimum; the EMD
+    # adjoint source is an angular envelope of the oscillating least-squares one (over
+    # the wavelets' span it turns twice, where the least-squares one turns 4-6 times)
+    shifts = np.arange(-200, 201, 20)
+    gs = config1_pairs(shifts, f_peak=8.0)
+    p = E.SolverParams(precision=E.F64, tol_res=1e-7, max_iter=10000000, sweeps_per_sync=4096)
+    log("41 shifts at 8 Hz: least squares and EMD")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    lsd, psi_l = E.lsd_misfit(plan, pcal, pobs)
+    emd, phi, u, info, mass, psi_e = _solve_all(plan, pcal, pobs)
+    lsd = lsd.cpu().numpy()
+    psi_l = unpack(psi_l.cpu().numpy(), desc)
+    psi_e = unpack(psi_e, desc)
+    for k in range(len(gs)):
+        log(f"  shift {shifts[k]:4d} ms: lsd {lsd[k]:.6e} emd {emd[k]:.6e} it={info['iters'][k]}")
+    lmin = [int(shifts[k]) for k in range(1, len(lsd) - 1) if lsd[k] < lsd[k - 1] and lsd[k] < lsd[k + 1]]
+    assert lmin == [-120, 0, 120] or lmin == [-100, 0, 100]
+    i0 = int(np.argmin(emd))
+    assert shifts[i0] == 0
+    slack = 1e-6 * emd.max()
+    assert np.all(np.diff(emd[:i0 + 1]) < slack) and np.all(np.diff(emd[i0:]) > -slack)
+    for sh in (40, 60, 80, 120):
+        k = int(np.flatnonzero(shifts == sh)[0])
+        ce, cl = _turns_in_span(psi_e[k], psi_l[k]), _turns_in_span(psi_l[k], psi_l[k])
+        log(f"  shift {sh} ms: turning points of the adjoint source, EMD {ce}, least squares {cl}")
+        assert ce == 2 and cl >= 4
+    plan.close()
+
+
 def _crop(g, r0, t0, nr=32, nt=128):
     pc = g.pcal[r0:r0 + nr, t0:t0 + nt].astype(np.float64)
     po = g.pobs[r0:r0 + nr, t0:t0 + nt].astype(np.float64)

@@ -259,6 +259,32 @@ def test_adjoint_matches_oracle_on_same_phi(precision, mode):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", [E.F32, E.F64])
+def test_lsd_matches_oracle(precision):
+    dtype = np.float64 if precision == E.F64 else np.float32
+    gs = ragged_batch(dtype)
+    p = E.SolverParams(precision=precision)
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    gbar = torch.linspace(-1.5, 2.0, len(gs), dtype=torch.float64)
+    value, psi = E.lsd_misfit(plan, pcal, pobs, gbar=gbar)
+    value_only, none = E.lsd_misfit(plan, pcal, pobs, with_adjoint=False)
+    torch.cuda.synchronize()
+    assert none is None
+    value, value_only = value.cpu().numpy(), value_only.cpu().numpy()
+    psis = unpack(psi.cpu().numpy(), desc)
+    for k, g in enumerate(gs):
+        f, grad = oracle.lsd(g.pcal, g.pobs, g.dx, g.dt)
+        # FP64 sums of the same differences in another order
+        assert value[k] == pytest.approx(f, rel=1e-13)
+        assert value_only[k] == value[k]
+        want = grad * float(gbar[k])
+        # FP32 output: the rounding of the FP64 value; values far below the field's
+        # peak may fall into (or below) the subnormal range
+        np.testing.assert_allclose(psis[k], want, rtol=1e-15 if precision == E.F64 else 1.2e-7,
+                                   atol=1e-300 if precision == E.F64 else 1e-30 * np.abs(want).max())
+    plan.close()
+
+
 def test_statuses_of_degenerate_gathers():
     base = random_small_pair(6, 20, 9)
     q = np.round(base.pcal * 1024) / 1024
