@@ -243,6 +243,20 @@ def info_numpy(info: torch.Tensor) -> np.ndarray:
     return np.frombuffer(info.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
 
 
+class WarmStart:
+    """Solver state carried between misfit evaluations of one batch (the evaluations
+    of an FWI loop): the flux u and potential phi of the last solve.  Each solve
+    starts from them and overwrites them; the first one starts cold."""
+
+    def __init__(self, plan: Plan):
+        self.u = plan.empty(2)
+        self.phi = plan.empty()
+        self.valid = False
+
+    def reset(self):
+        self.valid = False
+
+
 class EMDMisfit(torch.autograd.Function):
     """EMD misfit of a batch: forward = decompose + PDHG solve, returning the EMD of
     every gather; backward = the hand-written adjoint-source kernel (the dual
@@ -250,9 +264,15 @@ class EMDMisfit(torch.autograd.Function):
     to the observed data."""
 
     @staticmethod
-    def forward(ctx, pcal, pobs, plan: Plan):
+    def forward(ctx, pcal, pobs, plan: Plan, warm: WarmStart | None = None):
         s, mass = emd_decompose(plan, pcal, pobs)
-        emd, phi, _, info = emd_pdhg_solve(plan, s, mass=mass)
+        if warm is None:
+            emd, phi, _, info = emd_pdhg_solve(plan, s, mass=mass)
+        else:
+            emd, phi, _, info = emd_pdhg_solve(plan, s, phi=warm.phi, u=warm.u, warm_start=warm.valid,
+                                               mass=mass)
+            warm.valid = True
+            phi = phi.clone()  # the state moves on with the next evaluation
         ctx.plan = plan
         ctx.info = info
         ctx.save_for_backward(phi, pcal, pobs, mass)
@@ -262,8 +282,10 @@ class EMDMisfit(torch.autograd.Function):
     def backward(ctx, grad_out):
         phi, pcal, pobs, mass = ctx.saved_tensors
         psi = emd_adjoint_source(ctx.plan, phi, pcal, pobs, mass, gbar=grad_out)
-        return psi, None, None
+        return psi, None, None, None
 
 
-def emd_misfit(pcal, pobs, plan: Plan):
-    return EMDMisfit.apply(pcal, pobs, plan)
+def emd_misfit(pcal, pobs, plan: Plan, warm: WarmStart | None = None):
+    """EMD of every gather of the batch, differentiable with respect to pcal.  With a
+    WarmStart, the solve starts from the previous evaluation's flux and potential."""
+    return EMDMisfit.apply(pcal, pobs, plan, warm)
