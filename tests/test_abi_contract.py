@@ -82,6 +82,10 @@ def _create(L, lib, descs, batch_len, **over):
     ([(2, 5, 1.0, 1.0, 0)], 10, {"mass_mode": 3}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 1}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 3}, 1),         # unknown linesearch test
+    # a field region of a gather (nr rows of nt rounded up to 32) may not pass 1 GiB
+    ([(16384, 16385, 1.0, 1.0, 0)], 16384 * 16385, {}, 1),
+    ([(8192, 16385, 1.0, 1.0, 0)], 8192 * 16385, {"precision": 1}, 1),
+    ([(1, 1 << 31, 1.0, 1.0, 0)], 1 << 31, {}, 1),          # one trace of 2^31 samples: 8 GiB
     ([(2, 5, 1.0, 1.0, 0)], 10, {"max_ls_trials": -1}, 1),
 ])
 def test_plan_create_rejects_bad_arguments(descs, batch, over, code):
@@ -98,6 +102,16 @@ def test_plan_create_without_device_reports_device_error():
     L, lib = _lib()
     st, msg = _create(L, lib, [(2, 5, 1.0, 1.0, 0)], 10)
     assert st == 3, msg
+
+
+@pytest.mark.parametrize("desc,precision", [((16384, 16384, 1.0, 1.0, 0), 0), ((8192, 16384, 1.0, 1.0, 0), 1)])
+def test_field_regions_of_exactly_1_gib_pass_validation(desc, precision):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present (the GPU tests cover this size)")
+    L, lib = _lib()
+    st, msg = _create(L, lib, [desc], desc[0] * desc[1], precision=precision)
+    assert st == 3, msg  # past validation, then: no device on this host
 
 
 def test_null_pointers_are_rejected():
