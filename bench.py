@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=100000)
     ap.add_argument("--rows", type=int, default=0, help="rows per tile for every gather (0: autotune)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile height")
+    ap.add_argument("--ls", choices=["l2", "l1"], default="l2",
+                    help="linesearch test: Euclidean (default) or the l1 norms of Algorithm 1")
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--f64-gathers", type=int, default=2,
                     help="gathers of the workload solved by the plain FP64 path (bounded sample)")
@@ -139,7 +141,8 @@ def main():
     dev = torch.device("cuda", 0)
     pcal = torch.from_numpy(pcal_h).to(dev)
     pobs = torch.from_numpy(pobs_h).to(dev)
-    params = E.SolverParams(precision=E.F32, tol_res=args.tol, max_iter=args.max_iter)
+    params = E.SolverParams(precision=E.F32, tol_res=args.tol, max_iter=args.max_iter,
+                            ls_mode=E.LS_L1 if args.ls == "l1" else E.LS_L2)
     plan = E.Plan(desc, len(pcal_h), params)
     heights = None
     if args.rows:
@@ -195,11 +198,11 @@ def main():
     algo_bytes = BYTES_PER_CELL_ITER["f32"] * cell_updates
     achieved = algo_bytes / (sweep_ms / 1e3) / 1e9 if sweep_ms > 0 else 0.0
     traffic = None
-    if sweep_source_digest() == MEASURED_TRAFFIC["sweep_source_sha256_16"]:
+    if args.ls == "l2" and sweep_source_digest() == MEASURED_TRAFFIC["sweep_source_sha256_16"]:
         traffic = round(MEASURED_TRAFFIC["ratio"] * achieved, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_sweep<float, false>", "launches": int(sweeps),
+                "kernel": f"k_sweep<float, {'true' if args.ls == 'l1' else 'false'}>", "launches": int(sweeps),
                 "avg_launch_us": round(sweep_ms * 1e3 / max(sweeps, 1), 2),
                 "algo_bytes_per_launch": int(algo_bytes / max(sweeps, 1))}
 
@@ -281,6 +284,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wdesc, "gathers": len(gathers), "cells": cells,
                       "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
+                      "linesearch": args.ls,
                       "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
                       "tile_rows": heights if heights else (args.rows or 16)},
            "roofline": roofline, "cpu_baseline": cpu}

@@ -273,6 +273,13 @@ __device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, uint32_t off, T 
     }
 }
 
+// Cache policy of the field stores: non-temporal.  A sweep's output is read again
+// only by the next sweep, after the whole batch (gigabytes) has streamed through the
+// caches, so keeping it there only evicts lines that are still useful: the halo rows
+// the neighbouring tiles read shortly after (on the 64-gather batch a steady sweep
+// takes ~5 % less time and misses the L2 ~6 % less).  Loads keep the default policy.
+constexpr int kStoreNonTemporal = 2;
+
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, const T (&x)[Vec<T>::N])
 {
@@ -289,7 +296,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, c
         v[2] = (uint32_t)__double2loint(x[1]);
         v[3] = (uint32_t)__double2hiint(x[1]);
     }
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kStoreNonTemporal);
 }
 
 // Divergence of a flux on one row plus a source term:

@@ -239,6 +239,41 @@ def test_autograd_batch_and_finite_differences():
         cplan.close()
 
 
+def test_field_region_of_exactly_1_gib():
+    # one gather whose padded field region is exactly the 1 GiB that the sweep's 32-bit
+    # buffer offsets allow (16384 x 16384 FP32, 9 GiB of solver state): 20 iterations,
+    # then the oracle's operators recompute the reported residual and EMD from the
+    # returned flux (a wrapped offset would corrupt rows far down the gather)
+    n = 16384
+    ax = np.linspace(0.0, 1.0, n, dtype=np.float32)
+    g1 = lambda c: np.exp(-(ax - c) ** 2 / np.float32(0.01))
+    g = Gather(np.outer(g1(0.40), g1(0.45)), np.outer(g1(0.55), g1(0.50)), dx=1.0 / (n - 1),
+               dt=1.0 / (n - 1), label="16384x16384")
+    p = E.SolverParams(precision=E.F32, tol_res=0.0, max_iter=20, check_every=20)
+    log(f"one gather {n} x {n} FP32, 20 iterations")
+    plan, pcal, pobs, desc = make_plan([g], p)
+    del g
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    u = plan.empty(2)
+    emd, phi, u, info = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
+    torch.cuda.synchronize()
+    inf = E.info_numpy(info)[0]
+    assert E.GATHER_STATUS[inf["status"]] == "MAX_ITER" and inf["iters"] == 20
+    u_h = u.cpu().numpy()
+    s_h = s.cpu().numpy().reshape(n, n)
+    del u, phi, s, pcal, pobs
+    plan.close()
+    ux, ut = u_h[0].reshape(n, n), u_h[1].reshape(n, n)
+    d = oracle.div(ux, ut, 1.0 / (n - 1), 1.0 / (n - 1))
+    d += s_h
+    res = np.linalg.norm(d) / np.linalg.norm(s_h.astype(np.float64))
+    del d
+    e_ref, _ = oracle.emd_value(ux, ut, 1.0 / (n - 1), 1.0 / (n - 1))
+    log(f"  residual {inf['rel_res']:.6e} (oracle {res:.6e}), EMD {float(emd.cpu()[0]):.8e} (oracle {e_ref:.8e})")
+    assert inf["rel_res"] == pytest.approx(res, rel=1e-4)
+    assert float(emd.cpu()[0]) == pytest.approx(e_ref, rel=1e-5)
+
+
 def test_large_batch_fixed_budget():
     # 16 gathers of 4000 x 1600 (102 M cells, 3.7 GB of solver state): a fixed
     # budget, then the oracle's recomputation on sampled gathers

@@ -57,7 +57,7 @@ def test_time_weighting_in_1d_matches_the_closed_form():
     # 1D optimum scales as T^2 W + eps/2 T^3 Q, which the closed form gives exactly
     base = config1_pairs([40], nt=200, dt=1.0 / 199, f_peak=3.0, centre=0.45)[0]
     gs = [Gather(base.pcal, base.pobs, dx=1.0, dt=T / 199, label=f"T={T}") for T in (0.1, 1.0, 10.0)]
-    p = E.SolverParams(precision=E.F64, tol_res=1e-9, max_iter=4000000, sweeps_per_sync=4096)
+    p = E.SolverParams(precision=E.F64, tol_res=1e-7, max_iter=4000000, sweeps_per_sync=4096)
     plan, pcal, pobs, desc = make_plan(gs, p)
     s, mass = E.emd_decompose(plan, pcal, pobs)
     emd, phi, u, info = E.emd_pdhg_solve(plan, s, mass=mass)
@@ -75,9 +75,12 @@ def test_time_weighting_in_1d_matches_the_closed_form():
 
 
 def test_time_weighting_moves_transport_to_the_receiver_axis():
-    # with X = 1 fixed, a larger T makes time moves dearer, so the optimal flux moves
-    # more mass along the receivers (the adjoint source grows more continuous along
-    # that axis, as the paper observes for T = 0.1, 1, 10)
+    # with X = 1 fixed, a larger T makes time moves dearer: the optimal flux moves more
+    # mass across receivers (the adjoint source grows more continuous along that axis,
+    # as the paper observes for T = 0.1, 1, 10) and less along time.  Amounts in grid
+    # steps: sum |u^x| / dx (mass x receiver steps) and sum |u^t| / dt (mass x time
+    # steps); the second cannot grow with T (the optimal value is concave in the time
+    # cost and this is its slope), the first grows here by orders of magnitude
     base = config2_gather(seed=7, nr=40, nt=200, f_peak=2.0)
     gs = [Gather(base.pcal, base.pobs, dx=1.0 / 39, dt=T / 199, label=f"T={T}") for T in (0.1, 1.0, 10.0)]
     p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=2000000)
@@ -87,13 +90,14 @@ def test_time_weighting_moves_transport_to_the_receiver_axis():
     emd, phi, u, info = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
     torch.cuda.synchronize()
     us = unpack(u.cpu().numpy(), desc, 2)
-    share = []
+    xs, ts = [], []
     for k, g in enumerate(gs):
-        wx = np.abs(us[k][0]).sum() * g.dx
-        wt = np.abs(us[k][1]).sum() * g.dt
-        share.append(wx / (wx + wt))
-        log(f"  {g.label}: EMD {float(emd[k]):.6e}, share of transport along receivers {share[-1]:.3f}")
-    assert share[0] < share[1] < share[2]
+        xs.append(np.abs(us[k][0].astype(np.float64)).sum() / g.dx)
+        ts.append(np.abs(us[k][1].astype(np.float64)).sum() / g.dt)
+        log(f"  {g.label}: EMD {float(emd[k]):.6e}, transport along receivers {xs[-1]:.4e}, "
+            f"along time {ts[-1]:.4e} (grid steps x mass)")
+    assert xs[0] < xs[1] < xs[2]
+    assert ts[1] <= ts[0] * 1.01 and ts[2] < ts[1]
     e = emd.cpu().numpy()
     assert e[0] < e[1] < e[2]
     plan.close()
