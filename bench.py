@@ -29,7 +29,7 @@ BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi,
 # Bytes crossing the L2 boundary per sweep over the algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest; the traffic figure is null for any other source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "281cca39bc7d463e", "ratio": 1.133}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "5639a7b8fb80ea4e", "ratio": 1.078}
 
 
 def sweep_source_digest():
@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=100000)
     ap.add_argument("--rows", type=int, default=0, help="rows per tile for every gather (0: autotune)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile height")
+    ap.add_argument("--heights-from", default="", metavar="JSON",
+                    help="take the per-gather tile heights from an earlier bench line")
     ap.add_argument("--ls", choices=["l2", "l1"], default="l2",
                     help="linesearch test: Euclidean (default) or the l1 norms of Algorithm 1")
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
@@ -145,8 +147,16 @@ def main():
                             ls_mode=E.LS_L1 if args.ls == "l1" else E.LS_L2)
     plan = E.Plan(desc, len(pcal_h), params)
     heights = None
+    rows = None
     if args.rows:
         plan.set_tiling(args.rows)
+    elif args.heights_from:
+        # the per-gather heights an earlier (autotuned) run chose, to profile that run's
+        # configuration without the autotuner's own sweeps
+        with open(args.heights_from) as fh:
+            rows = json.load(fh)["config"]["tile_rows_per_gather"]
+        plan.set_gather_tiling(rows)
+        heights = {str(h): rows.count(h) for h in sorted(set(rows))}
     elif not args.no_autotune:
         # tile heights per size bucket, picked by the library's autotuner (untimed setup)
         s0, _ = E.emd_decompose(plan, pcal, pobs)
@@ -203,6 +213,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_sweep<float, {'true' if args.ls == 'l1' else 'false'}>", "launches": int(sweeps),
+                # one sweep = one launch per chain (the graph runs the chains
+                # concurrently); the figures are per sweep of the whole batch
                 "avg_launch_us": round(sweep_ms * 1e3 / max(sweeps, 1), 2),
                 "algo_bytes_per_launch": int(algo_bytes / max(sweeps, 1))}
 
@@ -286,7 +298,8 @@ def main():
                       "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
                       "linesearch": args.ls,
                       "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
-                      "tile_rows": heights if heights else (args.rows or 16)},
+                      "tile_rows": heights if heights else (args.rows or 16),
+                      "tile_rows_per_gather": plan.gather_tiling()},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
