@@ -122,6 +122,15 @@ typedef struct {
     double alpha;      /* last accepted primal step                        */
 } emd_solve_info;
 
+/* Solver state of one gather at the end of a solve: the step alpha_k and theta_k
+ * of its last accepted iteration k, and the counts (host struct).  With the flux u_k
+ * and potential phi_k the solve returned, it is all a resumed solve needs (see
+ * emd_pdhg_solve_resume). */
+typedef struct {
+    double alpha, theta;
+    int32_t iters, ls_trials;
+} emd_gather_state;
+
 /* Plan statistics (host struct filled by emd_plan_query). */
 typedef struct {
     int32_t ngather, tiles, rows_per_tile, samples_per_tile;
@@ -210,6 +219,24 @@ emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, voi
 emd_status emd_pdhg_solve(emd_plan* plan, const void* s, void* u, void* phi, int32_t warm_start,
                           const double* d_mass, double* d_emd, emd_solve_info* d_info,
                           hipStream_t stream);
+
+/* Checkpoint: the per-gather solver state at the end of the plan's last solve
+ * (h_state: host emd_gather_state[ngather]).  Together with that solve's u and phi
+ * it is a checkpoint of the iteration. */
+emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state);
+
+/* Resume: emd_pdhg_solve continued from a checkpoint instead of a cold start.
+ * u and phi (required) hold the checkpoint's flux and potential on entry and the
+ * final ones on return; h_state is the checkpoint's host emd_gather_state[ngather].
+ * Each gather continues from iteration iters with steps alpha, theta: the first
+ * sweep redoes the checkpointed iteration's primal update (the dual step was
+ * applied), which rebuilds the previous residual and the linesearch inner
+ * products, so a solve of K iterations resumed to 2K (max_iter counts from 0)
+ * reproduces a single solve of 2K iterations bitwise.  A gather with nothing to
+ * solve keeps that status; other statuses restart as running. */
+emd_status emd_pdhg_solve_resume(emd_plan* plan, const void* s, void* u, void* phi,
+                                 const emd_gather_state* h_state, const double* d_mass,
+                                 double* d_emd, emd_solve_info* d_info, hipStream_t stream);
 
 /* The same solve with the step sizes taken from a schedule instead of the
  * linesearch: iteration k of gather g uses alpha_{k+1} = d_alpha[g * ld_alpha + k]

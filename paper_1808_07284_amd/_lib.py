@@ -27,7 +27,8 @@ F32, F64 = 0, 1
 EXPORTED = ["emd_params_default", "emd_plan_create", "emd_plan_destroy", "emd_plan_set_params",
             "emd_plan_set_tiling", "emd_plan_set_gather_tiling", "emd_plan_get_gather_tiling",
             "emd_plan_autotune", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
-            "emd_pdhg_solve_replay", "emd_adjoint_source", "emd_lsd_misfit", "emd_status_string",
+            "emd_pdhg_solve_replay", "emd_solver_state", "emd_pdhg_solve_resume",
+            "emd_adjoint_source", "emd_lsd_misfit", "emd_status_string",
             "emd_last_error"]
 
 
@@ -49,6 +50,11 @@ class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("ls_trials", C.c_int32),
                 ("pad", C.c_int32), ("rel_res", C.c_double), ("emd", C.c_double),
                 ("transport", C.c_double), ("alpha", C.c_double)]
+
+
+class GatherState(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("theta", C.c_double), ("iters", C.c_int32),
+                ("ls_trials", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -87,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.emd_pdhg_solve.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
     lib.emd_pdhg_solve_replay.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_int32, vp, vp, vp]
     lib.emd_adjoint_source.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.emd_solver_state.argtypes = [vp, C.POINTER(GatherState)]
+    lib.emd_pdhg_solve_resume.argtypes = [vp, vp, vp, vp, C.POINTER(GatherState), vp, vp, vp, vp]
     lib.emd_lsd_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("emd_status_string", "emd_last_error"):

@@ -207,6 +207,31 @@ def emd_pdhg_solve_replay(plan: Plan, s, alpha, phi=None, u=None, warm_start=Fal
     return emd_out, phi, u, info_out
 
 
+def solver_state(plan: Plan):
+    """Checkpoint of the plan's last solve: per gather the last accepted step alpha,
+    theta, the iteration count and backtracking trials (with that solve's u and phi)."""
+    arr = (L.GatherState * plan.ngather)()
+    L.check(L.load().emd_solver_state(plan.handle, arr))
+    return arr
+
+
+def emd_pdhg_solve_resume(plan: Plan, s, state, u, phi, mass=None, emd_out=None, info_out=None):
+    """Continue a solve from a checkpoint (solver_state plus the u, phi it returned);
+    u and phi are updated in place.  K iterations resumed to 2K reproduce a single
+    solve of 2K bitwise."""
+    emd_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
+               if emd_out is None else emd_out)
+    info_out = (torch.empty(plan.ngather * INFO_DTYPE.itemsize, dtype=torch.uint8, device=plan.device)
+                if info_out is None else info_out)
+    plan._check(s, "s")
+    plan._check(phi, "phi")
+    plan._check(u, "u", (2,))
+    with torch.cuda.device(plan.device):
+        L.check(L.load().emd_pdhg_solve_resume(plan.handle, _ptr(s), _ptr(u), _ptr(phi), state, _ptr(mass),
+                                               _ptr(emd_out), _ptr(info_out), _stream(plan.device)))
+    return emd_out, phi, u, info_out
+
+
 def emd_adjoint_source(plan: Plan, phi, pcal=None, pobs=None, mass=None, gbar=None, psi_out=None):
     """Adjoint source psi = d EMD / d Pcal (Section 2.3), scaled by gbar [ngather]."""
     psi_out = plan.empty() if psi_out is None else psi_out

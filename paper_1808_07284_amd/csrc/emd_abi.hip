@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -76,6 +77,8 @@ struct emd_plan {
     GState* d_gst = nullptr;   // [2][ngather]
     int32_t* d_done = nullptr;
     double* d_adj = nullptr;   // [ngather][4]
+    ResumeRec* d_resume = nullptr;  // [ngather] checkpoint a resumed solve continues from
+    std::vector<GState> last_state;  // per-gather state at the end of the last solve
     int32_t* h_done = nullptr; // pinned
     int64_t workspace_bytes = 0;
 
@@ -463,8 +466,11 @@ emd_status enqueue_sweeps(emd_plan* plan, const Chains<T>& ch, int count, hipStr
 template <typename T>
 emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int warm,
                       const double* d_mass, const double* replay, int ld_replay, double* d_emd,
-                      emd_solve_info* d_info, hipStream_t stream)
+                      emd_solve_info* d_info, hipStream_t stream, const ResumeRec* h_resume = nullptr)
 {
+    if (h_resume)
+        HIP_TRY(hipMemcpyAsync(plan->d_resume, h_resume, sizeof(ResumeRec) * plan->ngather,
+                               hipMemcpyHostToDevice, stream));
     AuxArgs<T> a = aux_args<T>(plan);
     a.s_user = static_cast<const T*>(s);
     a.u_user_in = warm ? static_cast<const T*>(u) : nullptr;
@@ -474,6 +480,7 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     a.mass = d_mass;
     a.emd_out = d_emd;
     a.info_out = d_info;
+    a.resume = h_resume ? plan->d_resume : nullptr;
 
     launch_zero_counter(plan->d_done, stream);
     launch_copy_in<T>(a, warm, plan->grid, stream);
@@ -552,8 +559,12 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     HIP_TRY(hipMemcpyAsync(st.data(), plan->d_gst, sizeof(GState) * plan->ngather, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     int64_t cu = 0;
-    for (int g = 0; g < plan->ngather; ++g) cu += (int64_t)plan->desc[g].nr * plan->desc[g].nt * st[g].iters;
+    for (int g = 0; g < plan->ngather; ++g) {
+        const int64_t it0 = h_resume && st[g].status != ST_ZERO_SOURCE ? h_resume[g].iters : 0;
+        cu += (int64_t)plan->desc[g].nr * plan->desc[g].nt * std::max<int64_t>(st[g].iters - it0, 0);
+    }
     plan->last_cell_updates = cu;
+    plan->last_state = st;
     return EMD_SUCCESS;
 }
 
@@ -651,7 +662,8 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
     if (hipMalloc(&plan->d_fields, fbytes) != hipSuccess ||
         hipMalloc(&plan->d_gst, sizeof(GState) * 2 * ngather) != hipSuccess ||
         hipMalloc(&plan->d_done, sizeof(int32_t) * 64) != hipSuccess ||
-        hipMalloc(&plan->d_adj, sizeof(double) * 4 * ngather) != hipSuccess) {
+        hipMalloc(&plan->d_adj, sizeof(double) * 4 * ngather) != hipSuccess ||
+        hipMalloc(&plan->d_resume, sizeof(ResumeRec) * ngather) != hipSuccess) {
         std::string m = "cannot allocate the solver workspace (" + std::to_string(fbytes >> 20) + " MiB)";
         cleanup(EMD_SUCCESS);
         return fail(EMD_ERR_OUT_OF_MEMORY, m);
@@ -690,6 +702,7 @@ emd_status emd_plan_destroy(emd_plan* plan)
     if (plan->d_gst) (void)hipFree(plan->d_gst);
     if (plan->d_done) (void)hipFree(plan->d_done);
     if (plan->d_adj) (void)hipFree(plan->d_adj);
+    if (plan->d_resume) (void)hipFree(plan->d_resume);
     if (plan->h_done) (void)hipHostFree(plan->h_done);
     if (plan->ev0) (void)hipEventDestroy(plan->ev0);
     if (plan->ev1) (void)hipEventDestroy(plan->ev1);
@@ -934,6 +947,49 @@ emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* p
     if (plan->params.precision == EMD_F32)
         return solve_impl<float>(plan, s, u, phi, warm_start != 0, nullptr, d_alpha, ld_alpha, d_emd, d_info, stream);
     return solve_impl<double>(plan, s, u, phi, warm_start != 0, nullptr, d_alpha, ld_alpha, d_emd, d_info, stream);
+}
+
+static_assert(sizeof(emd_gather_state) == sizeof(ResumeRec) &&
+                  offsetof(emd_gather_state, iters) == offsetof(ResumeRec, iters),
+              "emd_gather_state mirrors the resume record");
+
+emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state)
+{
+    g_last_error.clear();
+    if (!plan || !h_state) return fail(EMD_ERR_NULL_POINTER, "plan or h_state is NULL");
+    if (plan->last_state.size() != (size_t)plan->ngather)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "the plan has not solved yet");
+    for (int g = 0; g < plan->ngather; ++g) {
+        const GState& s = plan->last_state[g];
+        h_state[g].alpha = s.alpha;
+        h_state[g].theta = s.theta;
+        h_state[g].iters = s.iters;
+        h_state[g].ls_trials = s.trials;
+    }
+    return EMD_SUCCESS;
+}
+
+emd_status emd_pdhg_solve_resume(emd_plan* plan, const void* s, void* u, void* phi,
+                                 const emd_gather_state* h_state, const double* d_mass,
+                                 double* d_emd, emd_solve_info* d_info, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (!s || !u || !phi || !h_state) return fail(EMD_ERR_NULL_POINTER, "s, u, phi and h_state are required");
+    if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
+    for (int g = 0; g < plan->ngather; ++g) {
+        const emd_gather_state& r = h_state[g];
+        if (!(r.alpha > 0.0) || !std::isfinite(r.alpha) || !std::isfinite(r.theta) || r.iters < 0 ||
+            r.ls_trials < 0)
+            return fail(EMD_ERR_INVALID_ARGUMENT, "h_state[" + std::to_string(g) + "] is not a solver state");
+    }
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    std::vector<ResumeRec> rec(plan->ngather);
+    std::memcpy(rec.data(), h_state, sizeof(ResumeRec) * plan->ngather);
+    if (plan->params.precision == EMD_F32)
+        return solve_impl<float>(plan, s, u, phi, 1, d_mass, nullptr, 0, d_emd, d_info, stream, rec.data());
+    return solve_impl<double>(plan, s, u, phi, 1, d_mass, nullptr, 0, d_emd, d_info, stream, rec.data());
 }
 
 emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal, const void* pobs,

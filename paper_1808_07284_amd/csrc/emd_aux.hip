@@ -135,6 +135,15 @@ __global__ __launch_bounds__(64) void k_gather_init(AuxArgs<T> a)
         status = ST_ZERO_SOURCE;
         st.rel_res = 0.0;
     }
+    if (a.resume && status == ST_RUNNING) {
+        // continue from the checkpointed iteration: its steps and counts; the first
+        // sweep (started == 0) redoes that iteration's primal update with alpha
+        const ResumeRec r = a.resume[g];
+        st.alpha = r.alpha;
+        st.theta = r.theta;
+        st.iters = r.iters;
+        st.trials = r.trials;
+    }
     st.status = status;
     if (threadIdx.x == 0) {
         a.gst[g] = st;

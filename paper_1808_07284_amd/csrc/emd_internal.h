@@ -84,6 +84,12 @@ struct GState {
     int32_t ls_base;   // l1 linesearch: index of the first candidate in the partials
 };
 
+// Where a resumed solve continues a gather from (the checkpointed iteration).
+struct ResumeRec {
+    double alpha, theta;
+    int32_t iters, trials;
+};
+
 struct SolveScalars {
     double eps, xi, zeta, delta, tol_res;
     int32_t max_iter, check_every, max_ls_trials, ls_mode;

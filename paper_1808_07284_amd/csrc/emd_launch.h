@@ -61,6 +61,7 @@ struct AuxArgs {
     int32_t* done;
     double* emd_out;      // [ngather] or NULL
     void* info_out;       // emd_solve_info[ngather] or NULL
+    const ResumeRec* resume;  // [ngather]: continue from a checkpoint, or NULL
     double eps, delta_unused, alpha_max_factor;
 };
 

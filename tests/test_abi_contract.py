@@ -154,7 +154,8 @@ def test_binding_structs_mirror_the_header():
     ctypes_of = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double}
     structs = _header_structs()
     pairs = {"emd_gather_desc": L.GatherDesc, "emd_params": L.Params,
-             "emd_solve_info": L.SolveInfo, "emd_plan_stats": L.PlanStats}
+             "emd_solve_info": L.SolveInfo, "emd_plan_stats": L.PlanStats,
+             "emd_gather_state": L.GatherState}
     assert set(pairs) <= set(structs)
     for hname, cls in pairs.items():
         assert [(n, ctypes_of[t]) for n, t in structs[hname]] == \

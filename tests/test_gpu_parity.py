@@ -383,6 +383,42 @@ def test_autotuned_tiling_is_valid_and_reusable():
         pl.close()
 
 
+@pytest.mark.parametrize("ls", [E.LS_L2, E.LS_L1])
+def test_checkpoint_resume_is_bitwise(ls):
+    # a solve of K iterations, checkpointed (solver state + its u, phi) and resumed to
+    # 2K, reproduces a single solve of 2K iterations bitwise
+    gs = ragged_batch(np.float32)
+    K = 150
+    p2 = E.SolverParams(precision=E.F32, max_iter=2 * K, tol_res=0.0, check_every=2 * K, ls_mode=ls)
+    p1 = E.SolverParams(precision=E.F32, max_iter=K, tol_res=0.0, check_every=K, ls_mode=ls)
+    plan, pcal, pobs, desc = make_plan(gs, p2)
+    with pytest.raises(E.EMDError):
+        E.solver_state(plan)  # nothing solved yet
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    u_ref = plan.empty(2)
+    e_ref, phi_ref, _, i_ref = E.emd_pdhg_solve(plan, s, u=u_ref, mass=mass)
+    torch.cuda.synchronize()
+    e_ref, phi_ref, u_ref, i_ref = (e_ref.cpu().numpy(), phi_ref.cpu().numpy(), u_ref.cpu().numpy(),
+                                    E.info_numpy(i_ref))
+    plan.set_params(p1)
+    u = plan.empty(2)
+    _, phi, _, _ = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
+    state = E.solver_state(plan)
+    assert [state[k].iters for k in range(len(gs))] == [K] * len(gs)
+    plan.set_params(p2)
+    e2, phi, u, i2 = E.emd_pdhg_solve_resume(plan, s, state, u, phi, mass=mass)
+    torch.cuda.synchronize()
+    i2 = E.info_numpy(i2)
+    log(f"  ls_mode={ls}: 2K iterations {i_ref['iters'].tolist()} resumed {i2['iters'].tolist()}, "
+        f"trials {i_ref['ls_trials'].tolist()} / {i2['ls_trials'].tolist()}")
+    np.testing.assert_array_equal(e2.cpu().numpy(), e_ref)
+    np.testing.assert_array_equal(phi.cpu().numpy(), phi_ref)
+    np.testing.assert_array_equal(u.cpu().numpy(), u_ref)
+    for f in ("status", "iters", "ls_trials", "rel_res", "emd", "transport", "alpha"):
+        np.testing.assert_array_equal(i2[f], i_ref[f])
+    plan.close()
+
+
 def test_repeat_solves_are_bitwise_deterministic():
     gs = ragged_batch(np.float32)
     p = E.SolverParams(precision=E.F32, max_iter=200, tol_res=0.0, check_every=200)
