@@ -9,6 +9,9 @@ current stream of the tensors' device.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
+import os
 from dataclasses import dataclass, fields
 
 import numpy as np
@@ -56,6 +59,22 @@ class SolverParams:
     @property
     def dtype(self) -> torch.dtype:
         return torch.float64 if self.precision == L.F64 else torch.float32
+
+
+def autotune_key(arch: str, rocm: str | None, precision: int, sizes) -> str:
+    """Cache key of a tile-height choice: device architecture, ROCm version, precision
+    and the (nr, nt) of every gather in batch order."""
+    h = hashlib.sha256(json.dumps([[int(a), int(b)] for a, b in sizes]).encode()).hexdigest()[:24]
+    return f"{arch}|rocm {rocm}|{'f64' if precision == L.F64 else 'f32'}|{len(sizes)} gathers|{h}"
+
+
+def _read_cache(path: str) -> dict:
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
 
 
 def _ptr(t):
@@ -125,14 +144,37 @@ class Plan:
         L.check(L.load().emd_plan_get_gather_tiling(self.handle, arr))
         return list(arr)
 
-    def autotune(self, s, sweeps: int = 0) -> list:
+    def autotune(self, s, sweeps: int = 0, cache: str | None = None) -> list:
         """Pick tile heights per size bucket by timing short fixed-step solves from the
         source s (the workspace is overwritten; the parameters are kept).  Returns the
-        chosen per-gather heights."""
+        chosen per-gather heights.
+
+        cache: a JSON file (default: the EMD_AUTOTUNE_CACHE environment variable, none if
+        unset) of earlier choices keyed by device architecture, ROCm version, precision
+        and the batch's gather sizes; a hit applies the stored heights without timing."""
         self._check(s, "s")
+        path = cache if cache is not None else os.environ.get("EMD_AUTOTUNE_CACHE")
+        key = None
+        if path:
+            props = torch.cuda.get_device_properties(self.device)
+            key = autotune_key(getattr(props, "gcnArchName", props.name), torch.version.hip,
+                               self.params.precision, [(d[0], d[1]) for d in self.descs])
+            entries = _read_cache(path)
+            rows = entries.get(key)
+            if rows is not None and len(rows) == self.ngather:
+                self.set_gather_tiling(rows)
+                return self.gather_tiling()
         with torch.cuda.device(self.device):
             L.check(L.load().emd_plan_autotune(self.handle, _ptr(s), int(sweeps), _stream(self.device)))
-        return self.gather_tiling()
+        rows = self.gather_tiling()
+        if path:
+            entries = _read_cache(path)
+            entries[key] = rows
+            tmp = f"{path}.{os.getpid()}.tmp"
+            with open(tmp, "w") as fh:
+                json.dump(entries, fh)
+            os.replace(tmp, path)
+        return rows
 
     def query(self) -> dict:
         s = L.PlanStats()

@@ -160,3 +160,18 @@ def test_binding_structs_mirror_the_header():
     for hname, cls in pairs.items():
         assert [(n, ctypes_of[t]) for n, t in structs[hname]] == \
             [(n, t) for n, t in cls._fields_], hname
+
+
+def test_autotune_cache_key():
+    from paper_1808_07284_amd.api import autotune_key
+    from paper_1808_07284_amd import F32, F64
+    k = autotune_key("gfx950", "7.0", F32, [(300, 2000), (200, 1500)])
+    assert k.startswith("gfx950|rocm 7.0|f32|2 gathers|")
+    assert k == autotune_key("gfx950", "7.0", F32, [(300, 2000), (200, 1500)])
+    # order, sizes, precision, architecture and ROCm version all separate entries
+    others = [autotune_key("gfx950", "7.0", F32, [(200, 1500), (300, 2000)]),
+              autotune_key("gfx950", "7.0", F32, [(300, 2000), (200, 1501)]),
+              autotune_key("gfx950", "7.0", F64, [(300, 2000), (200, 1500)]),
+              autotune_key("gfx942", "7.0", F32, [(300, 2000), (200, 1500)]),
+              autotune_key("gfx950", "7.2", F32, [(300, 2000), (200, 1500)])]
+    assert k not in others and len(set(others)) == len(others)

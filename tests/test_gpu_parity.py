@@ -383,6 +383,32 @@ def test_autotuned_tiling_is_valid_and_reusable():
         pl.close()
 
 
+def test_autotune_cache_hit_skips_the_timing(tmp_path, monkeypatch):
+    # the first plan times the heights and stores them under its key; a second plan of
+    # the same batch finds them in the cache (EMD_AUTOTUNE_CACHE) and times nothing
+    from synth import config3_batch
+    from paper_1808_07284_amd import _lib as L
+    gs = config3_batch()[:6]
+    p = E.SolverParams(precision=E.F32)
+    path = tmp_path / "tiles.json"
+    monkeypatch.setenv("EMD_AUTOTUNE_CACHE", str(path))
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    s, _ = E.emd_decompose(plan, pcal, pobs)
+    rows = plan.autotune(s, sweeps=8)
+    import json
+    entries = json.loads(path.read_text())
+    assert list(entries.values()) == [rows]
+    plan2, _, _, _ = make_plan(gs, p)
+    calls = []
+    lib = L.load()
+    real = lib.emd_plan_autotune
+    monkeypatch.setattr(lib, "emd_plan_autotune", lambda *a: calls.append(a) or real(*a))
+    assert plan2.autotune(s, sweeps=8) == rows
+    assert calls == [] and plan2.gather_tiling() == rows
+    plan.close()
+    plan2.close()
+
+
 @pytest.mark.parametrize("ls", [E.LS_L2, E.LS_L1])
 def test_checkpoint_resume_is_bitwise(ls):
     # a solve of K iterations, checkpointed (solver state + its u, phi) and resumed to
