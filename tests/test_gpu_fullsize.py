@@ -2,12 +2,14 @@
 (default tiling, FP32, stop rule).  The oracle cannot run these solves to
 convergence on the CPU, so it checks what it can compute one by one from the
 library's outputs -- the residual and EMD of the returned flux, the adjoint of the
-returned potential -- plus properties that hold at any size (exact symmetry), and
+returned potential, a duality bracket of the optimal transport cost around the
+returned transport -- plus properties that hold at any size (exact symmetry), and
 the 1D closed form for the single-trace study."""
 import numpy as np
 import pytest
 
 import oracle
+from certificate import transport_bounds
 from gpu_util import log, make_plan, unpack
 from synth import (config1_pairs, config2_gather, config3_batch, config4_batch, config5_batch,
                    Gather)
@@ -31,7 +33,7 @@ def _solve_all(plan, pcal, pobs):
             mass.cpu().numpy(), psi.cpu().numpy())
 
 
-def _check_gather(g, ux, ut, phi, psi, mass, emd, info, tol):
+def _check_gather(g, ux, ut, phi, psi, mass, emd, info, tol, gap=2e-3):
     """Recompute with the oracle's operators what the library reported."""
     ux = ux.astype(np.float64)
     ut = ut.astype(np.float64)
@@ -46,6 +48,14 @@ def _check_gather(g, ux, ut, phi, psi, mass, emd, info, tol):
     assert emd == pytest.approx(e, rel=1e-5)                 # EMD of the returned flux
     ref = oracle.adjoint(phi.astype(np.float64), g.pcal, g.pobs, mass, g.dx, g.dt)
     np.testing.assert_allclose(psi, ref, rtol=0, atol=4e-6 * np.abs(ref).max())
+    # duality: the returned potential, made 1-Lipschitz, bounds the optimal transport
+    # cost from below; the returned flux plus a transport of its residual, from above
+    lo, w, hi = transport_bounds(s, ux, ut, phi, g.dx, g.dt)
+    log(f"    transport {info['transport']:.8e} in [{lo:.8e}, {hi:.8e}], "
+        f"gap {(hi - lo) / hi:.2e}, flux below lower bound by {(lo - w) / hi:.2e}")
+    assert w == pytest.approx(info["transport"], rel=1e-6)
+    assert lo - (hi - w) <= w <= hi
+    assert (hi - lo) / hi <= gap
 
 
 def test_benchmark_batch_to_the_stop_rule():
@@ -60,6 +70,15 @@ def test_benchmark_batch_to_the_stop_rule():
     for k in (0, 17, 41, 63):
         log(f"  gather {k} {gs[k].nr}x{gs[k].nt}: it={info[k]['iters']} emd={emd[k]:.8e}")
         _check_gather(gs[k], us[k][0], us[k][1], phis[k], psis[k], mass[k], emd[k], info[k], 1e-5)
+    # every gather's transport inside its duality bracket
+    gaps = []
+    for k, g in enumerate(gs):
+        s, _, _, _ = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+        lo, w, hi = transport_bounds(s, us[k][0], us[k][1], phis[k], g.dx, g.dt)
+        assert lo - (hi - w) <= w <= hi
+        gaps.append((hi - lo) / hi)
+    log(f"  duality gap over the batch: median {np.median(gaps):.2e}, max {max(gaps):.2e}")
+    assert max(gaps) <= 2e-3
     # exact symmetry at full size: swapping predicted and observed negates s exactly,
     # and the iteration is odd in s with sign-symmetric rounding
     emd2, _, _, info2, _, _ = _solve_all(plan, pobs, pcal)
