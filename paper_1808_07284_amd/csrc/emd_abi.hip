@@ -792,16 +792,22 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
         }
         return code;
     };
-    // one untimed solve captures the graph of this tiling, the second is timed
+    // one untimed solve captures the graph of this tiling; the fastest of the next
+    // three is its time (one chunk is ~20 ms, where run-to-run noise is a few tenths
+    // of a percent, as large as the differences between neighbouring heights)
     auto timed = [&](float& ms) -> emd_status {
-        for (int r = 0; r < 2; ++r) {
+        ms = 0.f;
+        for (int r = 0; r < 4; ++r) {
             const emd_status e =
                 plan->params.precision == EMD_F32
                     ? solve_impl<float>(plan, s, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, stream)
                     : solve_impl<double>(plan, s, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, stream);
             if (e != EMD_SUCCESS) return e;
+            if (r == 0) continue;
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, plan->ev0, plan->ev1));
+            if (r == 1 || t < ms) ms = t;
         }
-        HIP_TRY(hipEventElapsedTime(&ms, plan->ev0, plan->ev1));
         return EMD_SUCCESS;
     };
     const int n = plan->ngather;
@@ -850,7 +856,11 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
             float ms = 0.f;
             st = timed(ms);
             if (st != EMD_SUCCESS) return restore(st);
-            if (ms < best * 0.997f) {
+            // The timing covers sweeps of the whole batch.  At the end of a solve the
+            // last gathers run alone and each launch lasts about as long as one
+            // wave's march over its rows, so taller tiles cost there what they save
+            // here: they must win by 1 %, shorter ones by 0.3 %.
+            if (ms < best * (c > cur ? 0.99f : 0.997f)) {
                 best = ms;
                 best_rows = trial;
             }
