@@ -183,13 +183,13 @@ emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows);
 
 /* Tile-height autotuner.  Puts the gathers in 3 x 3 size buckets (tertiles of nt
  * and of nr over the batch) and, bucket by bucket (largest first), tries heights
- * 8, 12, 16, 24 and 32 for that bucket, timing a fixed-step solve of `sweeps`
- * sweeps (even, 4..4096; 0 = 48) of the whole batch from the source s (as given to
+ * 8, 12 and 16 for that bucket, timing a fixed-step solve of `sweeps` sweeps (even,
+ * 4..4096; 0 = 48) of the whole batch from the source s (as given to
  * emd_pdhg_solve) in the production launch configuration (the fastest of three
- * runs after a warm-up), and keeps a shorter height when it is faster by more than
- * 0.3 %, a taller one by more than 1 % (taller tiles lengthen each launch of the
- * last few running gathers, which a whole-batch timing does not see).  The chosen
- * heights stay in the plan (read them
+ * runs after a warm-up), and keeps a height when it is faster by more than 0.3 %.
+ * (Taller tiles are not tried: they lengthen each launch of the last few running
+ * gathers, which a whole-batch timing does not see.)  The chosen heights stay in
+ * the plan (read them
  * with emd_plan_get_gather_tiling to reuse them).  The plan's parameters are left
  * unchanged; its workspace is overwritten; synchronises the device.  Timing-based,
  * so the choice can differ from run to run. */

@@ -838,7 +838,11 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
     float best = 0.f;
     st = timed(best);
     if (st != EMD_SUCCESS) return restore(st);
-    static const int kCand[] = {8, 12, 16, 24, 32};
+    // Taller tiles than the default are not tried: at the end of a solve the last
+    // gathers run alone and each launch lasts about one wave's march over its rows,
+    // which a whole-batch timing does not see; whenever such timings chose 24 or 32
+    // rows for a bucket, the full solve was slower.
+    static const int kCand[] = {8, 12, kDefaultRows};
     for (int bi = 0; bi < 9; ++bi) {
         const int b = order[bi];
         if (bcells[b] == 0) continue;
@@ -856,11 +860,7 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
             float ms = 0.f;
             st = timed(ms);
             if (st != EMD_SUCCESS) return restore(st);
-            // The timing covers sweeps of the whole batch.  At the end of a solve the
-            // last gathers run alone and each launch lasts about as long as one
-            // wave's march over its rows, so taller tiles cost there what they save
-            // here: they must win by 1 %, shorter ones by 0.3 %.
-            if (ms < best * (c > cur ? 0.99f : 0.997f)) {
+            if (ms < best * 0.997f) {
                 best = ms;
                 best_rows = trial;
             }
