@@ -60,7 +60,8 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        lib = C.CDLL(build())
+        # EMD_ORACLE_LIB: another build of emd_oracle.c (e.g. with sanitizers)
+        lib = C.CDLL(os.environ.get("EMD_ORACLE_LIB") or build())
         dp = C.POINTER(C.c_double)
         lib.oracle_grad.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
         lib.oracle_div.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]

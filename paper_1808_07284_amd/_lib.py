@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libemd_mi355x.so")
+# EMD_MI355X_LIB selects another build of the same sources (e.g. one with host-side
+# sanitizers); by default the in-tree build is loaded
+LIB_PATH = os.environ.get("EMD_MI355X_LIB") or os.path.join(PKG, "libemd_mi355x.so")
 
 # call status
 EMD_SUCCESS = 0

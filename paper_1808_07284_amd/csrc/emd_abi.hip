@@ -6,6 +6,7 @@
 // PDHG iteration for the whole batch (replayed from a captured HIP graph in chunks
 // of sweeps_per_sync launches) and reads the finished-gather count between chunks.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cstddef>
@@ -37,6 +38,15 @@ emd_status fail(emd_status st, const std::string& msg)
         if (e_ != hipSuccess)                                                                 \
             return fail(EMD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
     } while (0)
+
+// A named host range around each compute call, seen by rocprofv3 --marker-trace
+// (a no-op when no tool is attached).
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kDefaultRows = 16;
@@ -537,6 +547,10 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
                 if (cst != EMD_SUCCESS) return cst;
                 table_cells = live;
                 ++rebuilds;
+                const std::string mark = "emd: sweep tables narrowed after " + std::to_string(sweeps) +
+                                         " sweeps, running gathers: " +
+                                         std::to_string(plan->ngather - out);
+                roctxMarkA(mark.c_str());
             }
         }
         const int count = (int)std::min<int64_t>(chunk, max_sweeps - sweeps);
@@ -769,6 +783,7 @@ emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows)
 emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_plan_autotune");
     if (!plan || !s) return fail(EMD_ERR_NULL_POINTER, "plan or s is NULL");
     if (sweeps == 0) sweeps = 48;
     if (sweeps < 4 || sweeps > 4096 || (sweeps & 1))
@@ -900,6 +915,7 @@ emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, voi
                          void* f_out, void* g_out, double* d_mass, hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_decompose");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!pcal || !pobs || !s_out || !d_mass) return fail(EMD_ERR_NULL_POINTER, "pcal, pobs, s_out and d_mass are required");
     if (s_out == pcal || s_out == pobs) return fail(EMD_ERR_INVALID_ARGUMENT, "s_out aliases an input");
@@ -933,6 +949,7 @@ emd_status emd_pdhg_solve(emd_plan* plan, const void* s, void* u, void* phi, int
                           hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_pdhg_solve");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!s || !phi) return fail(EMD_ERR_NULL_POINTER, "s and phi are required");
     if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
@@ -948,6 +965,7 @@ emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* p
                                  double* d_emd, emd_solve_info* d_info, hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_pdhg_solve_replay");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!s || !phi || !d_alpha) return fail(EMD_ERR_NULL_POINTER, "s, phi and d_alpha are required");
     if (ld_alpha < plan->params.max_iter)
@@ -984,6 +1002,7 @@ emd_status emd_pdhg_solve_resume(emd_plan* plan, const void* s, void* u, void* p
                                  double* d_emd, emd_solve_info* d_info, hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_pdhg_solve_resume");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!s || !u || !phi || !h_state) return fail(EMD_ERR_NULL_POINTER, "s, u, phi and h_state are required");
     if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
@@ -1007,6 +1026,7 @@ emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal,
                               hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_adjoint_source");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!phi || !psi_out) return fail(EMD_ERR_NULL_POINTER, "phi and psi_out are required");
     if (plan->params.mass_mode == EMD_MASS_UNIT && (!pcal || !pobs || !d_mass))
@@ -1042,6 +1062,7 @@ emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, co
                           double* d_value, void* psi_out, hipStream_t stream)
 {
     g_last_error.clear();
+    const Range range("emd_lsd_misfit");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!pcal || !pobs || !d_value) return fail(EMD_ERR_NULL_POINTER, "pcal, pobs and d_value are required");
     if (psi_out && (psi_out == pcal || psi_out == pobs))
