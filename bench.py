@@ -128,8 +128,8 @@ def main():
         print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the batch shards by gather across GPUs, not built here)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (a batch "
+                                   "would shard by gather across GPUs; no multi-GPU path exists)"}))
         sys.exit(2)
 
     import torch

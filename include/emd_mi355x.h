@@ -63,7 +63,7 @@ typedef int32_t emd_status;
 #define EMD_ERR_DEVICE 3           /* the current device is not gfx950 / not the plan's */
 #define EMD_ERR_HIP 4              /* a HIP runtime call failed                         */
 #define EMD_ERR_OUT_OF_MEMORY 5    /* workspace allocation failed                       */
-#define EMD_ERR_UNSUPPORTED 6      /* valid request that this build does not implement  */
+#define EMD_ERR_UNSUPPORTED 6      /* valid request that the library does not implement */
 
 /* per-gather solve status, written into emd_solve_info.status */
 #define EMD_GATHER_RUNNING 0
