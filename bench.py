@@ -88,10 +88,17 @@ def cpu_baseline(gathers, iters, threads):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         cu = sum(ex.map(one, srcs))
     el = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": cu / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} gathers of the workload ({sum(g.cells for g in sample)} cells), "
                       f"{iters} fixed PDHG-linesearch iterations each, one gather per thread, "
-                      f"{el:.1f} s wall"}
+                      f"{el:.1f} s wall",
+            "host": f"{model}, {os.cpu_count()} logical CPUs"}
 
 
 def main():
