@@ -61,11 +61,17 @@ class SolverParams:
         return torch.float64 if self.precision == L.F64 else torch.float32
 
 
+# revision of the autotuner's candidate heights and timing rule: a cached choice made
+# by another revision is not reused
+AUTOTUNE_REVISION = 2
+
+
 def autotune_key(arch: str, rocm: str | None, precision: int, sizes) -> str:
-    """Cache key of a tile-height choice: device architecture, ROCm version, precision
-    and the (nr, nt) of every gather in batch order."""
+    """Cache key of a tile-height choice: device architecture, ROCm version, precision,
+    the (nr, nt) of every gather in batch order and the autotuner's revision."""
     h = hashlib.sha256(json.dumps([[int(a), int(b)] for a, b in sizes]).encode()).hexdigest()[:24]
-    return f"{arch}|rocm {rocm}|{'f64' if precision == L.F64 else 'f32'}|{len(sizes)} gathers|{h}"
+    return (f"{arch}|rocm {rocm}|{'f64' if precision == L.F64 else 'f32'}|{len(sizes)} gathers|{h}"
+            f"|tuner {AUTOTUNE_REVISION}")
 
 
 def _read_cache(path: str) -> dict:

@@ -166,7 +166,9 @@ def test_autotune_cache_key():
     from paper_1808_07284_amd.api import autotune_key
     from paper_1808_07284_amd import F32, F64
     k = autotune_key("gfx950", "7.0", F32, [(300, 2000), (200, 1500)])
+    from paper_1808_07284_amd.api import AUTOTUNE_REVISION
     assert k.startswith("gfx950|rocm 7.0|f32|2 gathers|")
+    assert k.endswith(f"|tuner {AUTOTUNE_REVISION}")
     assert k == autotune_key("gfx950", "7.0", F32, [(300, 2000), (200, 1500)])
     # order, sizes, precision, architecture and ROCm version all separate entries
     others = [autotune_key("gfx950", "7.0", F32, [(200, 1500), (300, 2000)]),
