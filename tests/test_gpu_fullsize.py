@@ -293,6 +293,57 @@ def test_field_region_of_exactly_1_gib():
     assert float(emd.cpu()[0]) == pytest.approx(e_ref, rel=1e-5)
 
 
+def test_reflections_and_scaling_of_full_size_gathers():
+    # Properties of the optimum that hold at any size: reversing a gather along the
+    # receivers or along time leaves the transport cost unchanged (the discrete
+    # problem maps onto itself), and at eps = 0 it scales with the data.  Eight
+    # gathers of the benchmark batch, cut to their first 70 % of receivers so that
+    # the shot is off-centre, each also reversed both ways and scaled by 4, solved
+    # together to the 1e-5 stop rule in FP32.
+    base = []
+    for g in config3_batch()[:8]:
+        m = int(0.7 * g.nr)
+        base.append(Gather(g.pcal[:m].copy(), g.pobs[:m].copy(), 1.0 / (m - 1), g.dt, g.label))
+    gs = list(base)
+    for axis in (0, 1):
+        gs += [Gather(np.flip(g.pcal, axis).copy(), np.flip(g.pobs, axis).copy(), g.dx, g.dt,
+                      f"{g.label} reversed {axis}") for g in base]
+    gs += [Gather(4 * g.pcal, 4 * g.pobs, g.dx, g.dt, f"{g.label} x4") for g in base]
+    p = E.SolverParams(precision=E.F32, eps=0.0, tol_res=1e-5, max_iter=100000)
+    log(f"{len(gs)} gathers ({sum(g.cells for g in gs)} cells), eps = 0, to 1e-5")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+    assert np.all(info["status"] == E.GATHER_STATUS.index("CONVERGED"))
+    np.testing.assert_array_equal(emd, info["transport"])   # eps = 0: EMD is the transport
+    us, phis = unpack(u, desc, 2), unpack(phi, desc)
+    n = len(base)
+    brackets = []
+    for k, g in enumerate(gs):
+        s, _, _, _ = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+        lo, w, hi = transport_bounds(s, us[k][0], us[k][1], phis[k], g.dx, g.dt)
+        assert lo - (hi - w) <= w <= hi
+        brackets.append((lo, w, hi))
+    gaps = [(hi - lo) / hi for lo, w, hi in brackets]
+    tr = info["transport"]
+    rev0 = np.abs(tr[n:2 * n] / tr[:n] - 1)
+    rev1 = np.abs(tr[2 * n:3 * n] / tr[:n] - 1)
+    scl = np.abs(tr[3 * n:] / (4 * tr[:n]) - 1)
+    log(f"  relative change: reversed receivers max {rev0.max():.2e}, reversed time "
+        f"max {rev1.max():.2e}, scaled by 4 max {scl.max():.2e}")
+    log(f"  duality gaps: {' '.join(f'{x:.1e}' for x in gaps)}")
+    # the mirror images take nearly the same path (only the order of the FP32 sums
+    # differs); the scaled gathers take another path, and at eps = 0 the 1e-5
+    # residual leaves the transport within its certified bracket, not closer
+    assert rev0.max() <= 1e-4 and rev1.max() <= 1e-4
+    for k in range(n):
+        lo1, _, hi1 = brackets[k]
+        lo4, _, hi4 = brackets[3 * n + k]
+        assert max(lo1, lo4 / 4) <= min(hi1, hi4 / 4)     # W1(4 s) = 4 W1(s): overlap
+        assert scl[k] <= gaps[k] + gaps[3 * n + k]
+    assert max(gaps) <= 2e-2
+    plan.close()
+
+
 def test_large_batch_fixed_budget():
     # 16 gathers of 4000 x 1600 (102 M cells, 3.7 GB of solver state): a fixed
     # budget, then the oracle's recomputation on sampled gathers

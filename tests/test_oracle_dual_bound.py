@@ -111,3 +111,41 @@ def test_oracle_optimum_certified_on_a_40x400_gather(oracle_mod):
     assert lo_neg < 0.5 * lo
     _, w_half, _ = transport_bounds(s, 0.5 * r.ux, 0.5 * r.ut, r.phi, g.dx, g.dt)
     assert w_half < 0.6 * lo
+
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_reflection_maps_the_iteration_onto_itself(oracle_mod, axis):
+    # With div = -grad^T, reversing a gather along either axis maps the discrete
+    # problem onto itself (the flux changes sign and moves to the mirrored edge, the
+    # potential is mirrored), so Algorithm 1 takes the same steps and reaches the same
+    # transport, up to the order of the sums.  The boundary rows of the divergence as
+    # printed would break this symmetry.
+    g = random_small_pair(16, 120, 31)
+    out = []
+    for pc, po in ((g.pcal, g.pobs), (np.flip(g.pcal, axis).copy(), np.flip(g.pobs, axis).copy())):
+        s, _, _, _ = oracle_mod.decompose(pc, po, g.dx, g.dt)
+        r = oracle_mod.solve(s, g.dx, g.dt, oracle_mod.Params(tol_res=1e-6, max_iter=400000))
+        assert r.status == oracle_mod.CONVERGED
+        out.append((r, transport_bounds(s, r.ux, r.ut, r.phi, g.dx, g.dt)))
+    (r0, (lo0, w0, hi0)), (r1, (lo1, w1, hi1)) = out
+    assert r1.iters == r0.iters and r1.ls_trials == r0.ls_trials
+    assert r1.transport == pytest.approx(r0.transport, rel=1e-10)
+    assert max(lo0, lo1) <= min(hi0, hi1)              # and the brackets agree
+    np.testing.assert_allclose(np.flip(r1.phi, axis), r0.phi, rtol=0,
+                               atol=1e-9 * np.abs(r0.phi).max())
+
+
+def test_transport_is_homogeneous_in_the_data_at_zero_eps(oracle_mod):
+    # W1(c s) = c W1(s): at eps = 0 the optimum scales with the data (the iteration
+    # does not: the shrink threshold is alpha whatever the scale)
+    g = config2_gather(nr=16, nt=120, f_peak=4.0, dtype=np.float64)
+    s, _, _, _ = oracle_mod.decompose(g.pcal, g.pobs, g.dx, g.dt)
+    vals = []
+    for c in (1.0, 8.0):
+        r = oracle_mod.solve(c * s, g.dx, g.dt, oracle_mod.Params(eps=0.0, tol_res=1e-6, max_iter=400000))
+        assert r.status == oracle_mod.CONVERGED
+        lo, w, hi = transport_bounds(c * s, r.ux, r.ut, r.phi, g.dx, g.dt)
+        assert lo <= w * (1 + 1e-12) and (hi - lo) / hi <= 2e-3
+        vals.append(w / c)
+    assert vals[1] == pytest.approx(vals[0], rel=2e-5)
