@@ -344,6 +344,31 @@ def test_reflections_and_scaling_of_full_size_gathers():
     plan.close()
 
 
+def test_l1_linesearch_to_the_stop_rule_at_full_size():
+    # the linesearch test with the l1 norms printed in Algorithm 1, on eight gathers
+    # of the benchmark batch to the 1e-5 stop rule: the same optimum as the
+    # Euclidean test, each transport inside its duality bracket
+    gs = config3_batch()[:8]
+    res = {}
+    for ls in (E.LS_L2, E.LS_L1):
+        p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=100000, ls_mode=ls)
+        plan, pcal, pobs, desc = make_plan(gs, p)
+        emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
+        assert np.all(info["status"] == E.GATHER_STATUS.index("CONVERGED"))
+        res[ls] = (emd, info)
+        if ls == E.LS_L1:
+            us, phis = unpack(u, desc, 2), unpack(phi, desc)
+            for k, g in enumerate(gs):
+                s, _, _, _ = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+                lo, w, hi = transport_bounds(s, us[k][0], us[k][1], phis[k], g.dx, g.dt)
+                assert lo - (hi - w) <= w <= hi and (hi - lo) / hi <= 2e-3
+        plan.close()
+    rel = np.abs(res[E.LS_L1][0] / res[E.LS_L2][0] - 1)
+    log(f"  l1 test: iterations {res[E.LS_L1][1]['iters'].tolist()} (Euclidean "
+        f"{res[E.LS_L2][1]['iters'].tolist()}), EMD change max {rel.max():.2e}")
+    assert rel.max() <= 1e-4
+
+
 def test_large_batch_fixed_budget():
     # 16 gathers of 4000 x 1600 (102 M cells, 3.7 GB of solver state): a fixed
     # budget, then the oracle's recomputation on sampled gathers
