@@ -125,13 +125,15 @@ typedef struct {
     double alpha;      /* last accepted primal step                        */
 } emd_solve_info;
 
-/* Solver state of one gather at the end of a solve: the step alpha_k and theta_k
- * of its last accepted iteration k, and the counts (host struct).  With the flux u_k
- * and potential phi_k the solve returned, it is all a resumed solve needs (see
- * emd_pdhg_solve_resume). */
+/* Solver state of one gather at the end of a solve (host struct): the step alpha_k
+ * and theta_k of its last accepted iteration k, the counts, and its outcome (status,
+ * and for a finished gather the residual, EMD and transport it reported).  With the
+ * flux u_k and potential phi_k the solve returned, it is all a resumed solve needs
+ * (see emd_pdhg_solve_resume). */
 typedef struct {
     double alpha, theta;
-    int32_t iters, ls_trials;
+    int32_t iters, ls_trials, status, pad;
+    double rel_res, emd, transport;
 } emd_gather_state;
 
 /* Plan statistics (host struct filled by emd_plan_query). */
@@ -238,8 +240,12 @@ emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state);
  * sweep redoes the checkpointed iteration's primal update (the dual step was
  * applied), which rebuilds the previous residual and the linesearch inner
  * products, so a solve of K iterations resumed to 2K (max_iter counts from 0)
- * reproduces a single solve of 2K iterations bitwise.  A gather with nothing to
- * solve keeps that status; other statuses restart as running. */
+ * reproduces a single solve of 2K iterations bitwise.  A gather whose checkpointed
+ * status is RUNNING or MAX_ITER continues; any other status (it met the stop rule,
+ * or failed) is final: the gather is not iterated, keeps its status, residual, EMD
+ * and transport, and its u and phi pass through unchanged, as in the uninterrupted
+ * solve.  (A gather whose source is zero reports ZERO_SOURCE either way.)  alpha
+ * must be finite and > 0 for the gathers that continue. */
 emd_status emd_pdhg_solve_resume(emd_plan* plan, const void* s, void* u, void* phi,
                                  const emd_gather_state* h_state, const double* d_mass,
                                  double* d_emd, emd_solve_info* d_info, hipStream_t stream);

@@ -56,7 +56,8 @@ class SolveInfo(C.Structure):
 
 class GatherState(C.Structure):
     _fields_ = [("alpha", C.c_double), ("theta", C.c_double), ("iters", C.c_int32),
-                ("ls_trials", C.c_int32)]
+                ("ls_trials", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32),
+                ("rel_res", C.c_double), ("emd", C.c_double), ("transport", C.c_double)]
 
 
 class PlanStats(C.Structure):

@@ -978,7 +978,10 @@ emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* p
 }
 
 static_assert(sizeof(emd_gather_state) == sizeof(ResumeRec) &&
-                  offsetof(emd_gather_state, iters) == offsetof(ResumeRec, iters),
+                  offsetof(emd_gather_state, iters) == offsetof(ResumeRec, iters) &&
+                  offsetof(emd_gather_state, status) == offsetof(ResumeRec, status) &&
+                  offsetof(emd_gather_state, rel_res) == offsetof(ResumeRec, rel_res) &&
+                  offsetof(emd_gather_state, transport) == offsetof(ResumeRec, transport),
               "emd_gather_state mirrors the resume record");
 
 emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state)
@@ -993,6 +996,11 @@ emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state)
         h_state[g].theta = s.theta;
         h_state[g].iters = s.iters;
         h_state[g].ls_trials = s.trials;
+        h_state[g].status = s.status;
+        h_state[g].pad = 0;
+        h_state[g].rel_res = s.rel_res;
+        h_state[g].emd = s.emd;
+        h_state[g].transport = s.transport;
     }
     return EMD_SUCCESS;
 }
@@ -1008,8 +1016,10 @@ emd_status emd_pdhg_solve_resume(emd_plan* plan, const void* s, void* u, void* p
     if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
     for (int g = 0; g < plan->ngather; ++g) {
         const emd_gather_state& r = h_state[g];
-        if (!(r.alpha > 0.0) || !std::isfinite(r.alpha) || !std::isfinite(r.theta) || r.iters < 0 ||
-            r.ls_trials < 0)
+        const bool cont = r.status == EMD_GATHER_RUNNING || r.status == EMD_GATHER_MAX_ITER;
+        if (r.status < EMD_GATHER_RUNNING || r.status > EMD_GATHER_MASS_IMBALANCE || r.iters < 0 ||
+            r.ls_trials < 0 ||
+            (cont && (!(r.alpha > 0.0) || !std::isfinite(r.alpha) || !std::isfinite(r.theta))))
             return fail(EMD_ERR_INVALID_ARGUMENT, "h_state[" + std::to_string(g) + "] is not a solver state");
     }
     emd_status st = check_device(plan);

@@ -143,6 +143,14 @@ __global__ __launch_bounds__(64) void k_gather_init(AuxArgs<T> a)
         st.theta = r.theta;
         st.iters = r.iters;
         st.trials = r.trials;
+        if (r.status != ST_RUNNING && r.status != ST_MAX_ITER) {
+            // the gather had finished: it keeps its outcome and is never swept, so
+            // the u and phi copied in above are what the solve returns for it
+            status = r.status;
+            st.rel_res = r.rel_res;
+            st.emd = r.emd;
+            st.transport = r.transport;
+        }
     }
     st.status = status;
     if (threadIdx.x == 0) {

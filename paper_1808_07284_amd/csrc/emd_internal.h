@@ -84,10 +84,12 @@ struct GState {
     int32_t ls_base;   // l1 linesearch: index of the first candidate in the partials
 };
 
-// Where a resumed solve continues a gather from (the checkpointed iteration).
+// Where a resumed solve continues a gather from (the checkpointed iteration), or
+// the outcome it keeps if the gather had finished.
 struct ResumeRec {
     double alpha, theta;
-    int32_t iters, trials;
+    int32_t iters, trials, status, pad;
+    double rel_res, emd, transport;
 };
 
 struct SolveScalars {

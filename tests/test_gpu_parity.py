@@ -11,6 +11,8 @@ Tolerances:
 * decompose / adjoint on identical inputs: FP32 within a few ulps (1e-6 relative),
   FP64 within 1e-12.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -437,6 +439,48 @@ def test_checkpoint_resume_is_bitwise(ls):
     i2 = E.info_numpy(i2)
     log(f"  ls_mode={ls}: 2K iterations {i_ref['iters'].tolist()} resumed {i2['iters'].tolist()}, "
         f"trials {i_ref['ls_trials'].tolist()} / {i2['ls_trials'].tolist()}")
+    np.testing.assert_array_equal(e2.cpu().numpy(), e_ref)
+    np.testing.assert_array_equal(phi.cpu().numpy(), phi_ref)
+    np.testing.assert_array_equal(u.cpu().numpy(), u_ref)
+    for f in ("status", "iters", "ls_trials", "rel_res", "emd", "transport", "alpha"):
+        np.testing.assert_array_equal(i2[f], i_ref[f])
+    plan.close()
+
+
+@pytest.mark.parametrize("ls", [E.LS_L2, E.LS_L1])
+def test_resume_keeps_finished_gathers_and_continues_the_rest(ls):
+    # with the stop rule on, a checkpoint taken when some gathers have converged and
+    # others have not: resumed (twice, in two legs) it reproduces the uninterrupted
+    # solve bitwise -- the converged gathers are not iterated again
+    gs = ragged_batch(np.float32)
+    z = gs[1]
+    gs.append(type(z)(z.pcal.copy(), z.pcal.copy(), z.dx, z.dt, "zero source"))
+    N = 4000
+    pN = E.SolverParams(precision=E.F32, max_iter=N, tol_res=1e-4, ls_mode=ls)
+    plan, pcal, pobs, desc = make_plan(gs, pN)
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    u_ref = plan.empty(2)
+    e_ref, phi_ref, _, i_ref = E.emd_pdhg_solve(plan, s, u=u_ref, mass=mass)
+    torch.cuda.synchronize()
+    e_ref, phi_ref, u_ref, i_ref = (e_ref.cpu().numpy(), phi_ref.cpu().numpy(), u_ref.cpu().numpy(),
+                                    E.info_numpy(i_ref))
+    conv = i_ref["iters"][i_ref["status"] == E.GATHER_STATUS.index("CONVERGED")]
+    assert len(set(conv.tolist())) >= 2
+    K1 = int(np.sort(conv)[len(conv) // 2])          # some gathers finish before, some after
+    K2 = (K1 + int(conv.max())) // 2
+    u = plan.empty(2)
+    plan.set_params(dataclasses.replace(pN, max_iter=K1))
+    _, phi, _, i1 = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
+    st1 = E.info_numpy(i1)["status"]
+    assert (st1 == E.GATHER_STATUS.index("CONVERGED")).any() and (st1 == E.GATHER_STATUS.index("MAX_ITER")).any()
+    for kmax in (K2, N):
+        state = E.solver_state(plan)
+        plan.set_params(dataclasses.replace(pN, max_iter=kmax))
+        e2, phi, u, i2 = E.emd_pdhg_solve_resume(plan, s, state, u, phi, mass=mass)
+    torch.cuda.synchronize()
+    i2 = E.info_numpy(i2)
+    log(f"  ls_mode={ls}: legs to {K1}, {K2}, {N}; iterations {i_ref['iters'].tolist()} "
+        f"resumed {i2['iters'].tolist()}, statuses {i2['status'].tolist()}")
     np.testing.assert_array_equal(e2.cpu().numpy(), e_ref)
     np.testing.assert_array_equal(phi.cpu().numpy(), phi_ref)
     np.testing.assert_array_equal(u.cpu().numpy(), u_ref)
