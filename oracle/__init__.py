@@ -85,6 +85,8 @@ def _load():
                                        dp, C.c_int, C.c_double, dp]
         lib.oracle_lsd.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
         lib.oracle_lsd.restype = C.c_double
+        lib.oracle_restrict.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
+        lib.oracle_prolong.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
         lib.oracle_misfit.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp,
                                       C.c_int, C.POINTER(_Params), dp, dp, dp, dp,
                                       C.POINTER(_Info)]
@@ -212,6 +214,31 @@ def solve(s, dx, dt, params: Params | None = None, u0=None, phi0=None,
     return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
                        info.emd, info.transport,
                        tr[:info.iters].copy() if trace else None)
+
+
+def coarse_shape(nr, nt, fr, ft):
+    """Size of the coarse grid that groups fr receivers by ft samples."""
+    return (nr + fr - 1) // fr, (nt + ft - 1) // ft
+
+
+def restrict(fine, fr, ft):
+    """Block means of a fine [nr, nt] field on the coarse grid (multi-grid strategy,
+    Section 2.2)."""
+    fine = _f64(fine)
+    nr, nt = fine.shape
+    out = np.empty(coarse_shape(nr, nt, fr, ft))
+    _load().oracle_restrict(nr, nt, fr, ft, _p(fine), _p(out))
+    return out
+
+
+def prolong(uxc, utc, phic, nr, nt, fr, ft):
+    """Bilinear prolongation of a coarse (u^x, u^t, phi) to the fine [nr, nt] grid,
+    each on its own staggering."""
+    uxc, utc, phic = _f64(uxc), _f64(utc), _f64(phic)
+    assert uxc.shape == utc.shape == phic.shape == coarse_shape(nr, nt, fr, ft)
+    ux, ut, phi = np.empty((nr, nt)), np.empty((nr, nt)), np.empty((nr, nt))
+    _load().oracle_prolong(nr, nt, fr, ft, _p(uxc), _p(utc), _p(phic), _p(ux), _p(ut), _p(phi))
+    return ux, ut, phi
 
 
 def lsd(pcal, pobs, dx, dt):

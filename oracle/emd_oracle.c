@@ -501,3 +501,102 @@ double oracle_lsd(int nr, int nt, double dx, double dt, const double* pcal,
     }
     return 0.5 * cm * sum;
 }
+
+/* ------------------------------------------------------- coarse-to-fine grids */
+
+/* Grid transfer for the multi-grid strategy (the closing remark of Section 2.2:
+ * compute the EMD on a coarse grid first, then run the primal-dual method on the
+ * fine grid; Section 3.3 resamples each shot record and interpolates the primal
+ * variable back to the original grid).  The coarse grid groups fr receivers by ft
+ * samples; its spacings are fr dx and ft dt, so the flux (a time or receiver
+ * integral of the source) and the potential (a distance) keep their scale.
+ *
+ * Restriction: coarse cell (I, J) is the mean of the fine cells
+ * i in [fr I, min(fr I + fr, nr)), j in [ft J, min(ft J + ft, nt)). */
+void oracle_restrict(int nr, int nt, int fr, int ft, const double* fine, double* coarse)
+{
+    const int nrc = (nr + fr - 1) / fr, ntc = (nt + ft - 1) / ft;
+    for (int I = 0; I < nrc; ++I)
+        for (int J = 0; J < ntc; ++J) {
+            double sum = 0.0;
+            int count = 0;
+            for (int i = fr * I; i < fr * I + fr && i < nr; ++i)
+                for (int j = ft * J; j < ft * J + ft && j < nt; ++j) {
+                    sum += fine[(int64_t)i * nt + j];
+                    ++count;
+                }
+            coarse[(int64_t)I * ntc + J] = sum / count;
+        }
+}
+
+/* Linear interpolation along one axis, as a pair of sample indices and weights.
+ * Cell-centred samples (n of them): fine index i sits at coarse coordinate
+ * (i - (f - 1)/2) / f, clamped to [0, n - 1].  Edge samples (the flux along its own
+ * axis; edge k lies between cells k - 1 and k): fine edge i sits at i / f, and the
+ * coarse edges run from 0 to n, the two boundary edges carrying no flux (weight on
+ * them is weight on a zero).  k1 = -1 marks a zero sample. */
+static void axis_weights(int i, int f, int n, int edge, int* k0, int* k1, double* w0, double* w1)
+{
+    double x;
+    int hi;
+    if (edge) {
+        x = (double)i / f;
+        hi = n;
+    } else {
+        x = (i - 0.5 * (f - 1)) / f;
+        hi = n - 1;
+    }
+    if (x < 0.0) x = 0.0;
+    if (x > hi) x = hi;
+    int k = (int)floor(x);
+    if (k >= hi) k = hi > 0 ? hi - 1 : 0;
+    double w = x - k;
+    *k0 = k;
+    *k1 = (hi > 0) ? k + 1 : k;
+    *w0 = (hi > 0) ? 1.0 - w : 1.0;
+    *w1 = (hi > 0) ? w : 0.0;
+    if (edge) {
+        /* the boundary edges 0 and n carry zero flux */
+        if (*k0 == 0 || *k0 == n) *k0 = -1;
+        if (*k1 == 0 || *k1 == n) *k1 = -1;
+    }
+}
+
+static double sample2(const double* v, int ntc, int a, int b)
+{
+    return (a < 0 || b < 0) ? 0.0 : v[(int64_t)a * ntc + b];
+}
+
+/* Bilinear interpolation of one coarse field onto the fine grid; edge_r / edge_t
+ * say which axes hold edge samples. */
+static void prolong_field(int nrc, int ntc, int nr, int nt, int fr, int ft, int edge_r, int edge_t,
+                          const double* coarse, double* fine)
+{
+    for (int i = 0; i < nr; ++i) {
+        int a0, a1;
+        double wa0, wa1;
+        axis_weights(i, fr, nrc, edge_r, &a0, &a1, &wa0, &wa1);
+        for (int j = 0; j < nt; ++j) {
+            int b0, b1;
+            double wb0, wb1;
+            axis_weights(j, ft, ntc, edge_t, &b0, &b1, &wb0, &wb1);
+            fine[(int64_t)i * nt + j] = wa0 * wb0 * sample2(coarse, ntc, a0, b0) +
+                                        wa0 * wb1 * sample2(coarse, ntc, a0, b1) +
+                                        wa1 * wb0 * sample2(coarse, ntc, a1, b0) +
+                                        wa1 * wb1 * sample2(coarse, ntc, a1, b1);
+        }
+    }
+}
+
+/* Prolongation of a coarse solution (u^x, u^t, phi on the grid of oracle_restrict)
+ * to the fine grid: phi is cell-centred on both axes; u^x lives on the receiver
+ * edges and the time cell centres, u^t on the time edges and the receiver cell
+ * centres.  Any of the fine outputs may be NULL. */
+void oracle_prolong(int nr, int nt, int fr, int ft, const double* uxc, const double* utc,
+                    const double* phic, double* ux, double* ut, double* phi)
+{
+    const int nrc = (nr + fr - 1) / fr, ntc = (nt + ft - 1) / ft;
+    if (ux) prolong_field(nrc, ntc, nr, nt, fr, ft, 1, 0, uxc, ux);
+    if (ut) prolong_field(nrc, ntc, nr, nt, fr, ft, 0, 1, utc, ut);
+    if (phi) prolong_field(nrc, ntc, nr, nt, fr, ft, 0, 0, phic, phi);
+}
