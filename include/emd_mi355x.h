@@ -284,6 +284,36 @@ emd_status emd_adjoint_source(emd_plan* plan, const void* phi, const void* pcal,
 emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, const double* d_gbar,
                           double* d_value, void* psi_out, hipStream_t stream);
 
+/* Grid transfer for the multi-grid strategy (Section 2.2 closes on it: compute the
+ * EMD on a coarse grid first, then run the primal-dual method on the fine grid;
+ * Section 3.3 resamples each shot and interpolates the coarse solution back).
+ * `fine` and `coarse` are plans of the same gathers in the same order, same
+ * precision and device; the coarse gather g groups fr receivers by ft samples:
+ * its size must be ceil(nr/fr) x ceil(nt/ft), and its spacings should be fr dx
+ * and ft dt (then the flux, an integral of the source, and the potential, a
+ * distance, keep their scale, so no values are rescaled).  Buffers are batch
+ * buffers of each plan's layout; neither call synchronises.
+ *
+ * emd_restrict: coarse_out[I][J] = mean of fine_in over the block i in
+ *   [fr I, min(fr I + fr, nr)), j in [ft J, min(ft J + ft, nt)) (FP64 sum), for
+ *   each gather (use it on Pcal and on Pobs before emd_decompose on the coarse
+ *   plan).  coarse_out must not alias fine_in. */
+emd_status emd_restrict(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft,
+                        const void* fine_in, void* coarse_out, hipStream_t stream);
+
+/* emd_prolong: bilinear interpolation of a coarse solution onto the fine grid, for
+ * a warm start (emd_pdhg_solve with warm_start = 1).  Each field keeps its
+ * staggering: phi at cell centres (fine cell i at coarse coordinate
+ * (i - (fr - 1)/2)/fr, clamped to the coarse cells); u^x on the receiver edges
+ * (fine edge i, between cells i - 1 and i, at coarse coordinate i/fr on the coarse
+ * edges 0..ceil(nr/fr), of which the first and last are boundary edges with no
+ * flux) and at time cell centres; u^t likewise with the axes swapped.  u_c / u_f:
+ * [u^x | u^t] batches of the coarse / fine plan; phi_c / phi_f: batches.  Either
+ * output may be NULL (then its input is not read); outputs must not alias inputs. */
+emd_status emd_prolong(const emd_plan* coarse, const emd_plan* fine, int32_t fr, int32_t ft,
+                       const void* u_c, const void* phi_c, void* u_f, void* phi_f,
+                       hipStream_t stream);
+
 /* Human-readable name of a call status. */
 const char* emd_status_string(emd_status status);
 

@@ -30,8 +30,8 @@ EXPORTED = ["emd_params_default", "emd_plan_create", "emd_plan_destroy", "emd_pl
             "emd_plan_set_tiling", "emd_plan_set_gather_tiling", "emd_plan_get_gather_tiling",
             "emd_plan_autotune", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
             "emd_pdhg_solve_replay", "emd_solver_state", "emd_pdhg_solve_resume",
-            "emd_adjoint_source", "emd_lsd_misfit", "emd_status_string",
-            "emd_last_error"]
+            "emd_adjoint_source", "emd_lsd_misfit", "emd_restrict", "emd_prolong",
+            "emd_status_string", "emd_last_error"]
 
 
 class GatherDesc(C.Structure):
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.emd_solver_state.argtypes = [vp, C.POINTER(GatherState)]
     lib.emd_pdhg_solve_resume.argtypes = [vp, vp, vp, vp, C.POINTER(GatherState), vp, vp, vp, vp]
     lib.emd_lsd_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.emd_restrict.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
+    lib.emd_prolong.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("emd_status_string", "emd_last_error"):
             getattr(lib, name).restype = st

@@ -311,6 +311,105 @@ def lsd_misfit(plan: Plan, pcal, pobs, gbar=None, value_out=None, psi_out=None, 
     return value_out, psi_out
 
 
+def coarse_descs(descs, fr: int, ft: int):
+    """Descriptors of the coarse grid that groups fr receivers by ft samples: sizes
+    ceil(nr/fr) x ceil(nt/ft), spacings fr dx and ft dt, gathers packed back to back.
+    Returns (descs, batch_len)."""
+    out, off = [], 0
+    for nr, nt, dx, dt, _ in descs:
+        nrc, ntc = -(-int(nr) // fr), -(-int(nt) // ft)
+        out.append((nrc, ntc, float(dx) * fr, float(dt) * ft, off))
+        off += nrc * ntc
+    return out, off
+
+
+def restrict(fine: Plan, coarse: Plan, fr: int, ft: int, x, out=None):
+    """Block means of a fine batch field on the coarse plan's grid (emd_restrict)."""
+    fine._check(x, "x")
+    out = coarse.empty() if out is None else out
+    coarse._check(out, "out")
+    with torch.cuda.device(fine.device):
+        L.check(L.load().emd_restrict(fine.handle, coarse.handle, int(fr), int(ft), _ptr(x), _ptr(out),
+                                      _stream(fine.device)))
+    return out
+
+
+def prolong(coarse: Plan, fine: Plan, fr: int, ft: int, u_c, phi_c, u_out=None, phi_out=None):
+    """Bilinear prolongation of a coarse (u, phi) to the fine plan's grid, each field
+    on its own staggering (emd_prolong).  Returns (u, phi)."""
+    coarse._check(u_c, "u_c", (2,))
+    coarse._check(phi_c, "phi_c")
+    u_out = fine.empty(2) if u_out is None else u_out
+    phi_out = fine.empty() if phi_out is None else phi_out
+    fine._check(u_out, "u_out", (2,))
+    fine._check(phi_out, "phi_out")
+    with torch.cuda.device(fine.device):
+        L.check(L.load().emd_prolong(coarse.handle, fine.handle, int(fr), int(ft), _ptr(u_c), _ptr(phi_c),
+                                     _ptr(u_out), _ptr(phi_out), _stream(fine.device)))
+    return u_out, phi_out
+
+
+class Multigrid:
+    """Coarse-to-fine solve (the multi-grid strategy of Section 2.2; Section 3.3
+    resamples each shot and interpolates the coarse solution back).  `factors` lists,
+    from the fine plan down, how each coarser level groups the receivers and samples
+    of the level above it.  The data are restricted level by level (block means),
+    the coarsest level is solved cold, and each solution, prolonged bilinearly
+    (u and phi), starts the solve of the next finer level; the fine solve itself is
+    left to the caller, who warm-starts it from (u, phi) written by start().  The
+    coarse plans are built once, with the fine plan's parameters unless given."""
+
+    def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None):
+        self.fine = plan
+        self.levels = []  # (coarse plan, fr, ft), finest first
+        descs = plan.descs
+        for fr, ft in factors:
+            cd, n = coarse_descs(descs, int(fr), int(ft))
+            self.levels.append((Plan(cd, n, params or plan.params, device=plan.device), int(fr), int(ft)))
+            descs = cd
+        self.last_info = []  # per level, coarsest first: the solve info of the last start()
+
+    def close(self):
+        for cp, _, _ in self.levels:
+            cp.close()
+
+    def start(self, pcal, pobs, u, phi):
+        """Solve the coarse levels for (pcal, pobs) and write the prolonged start of the
+        fine solve into u ([2, N]) and phi ([N])."""
+        data, finer = [], self.fine
+        pc, po = pcal, pobs
+        for cp, fr, ft in self.levels:
+            pc, po = restrict(finer, cp, fr, ft, pc), restrict(finer, cp, fr, ft, po)
+            data.append((pc, po))
+            finer = cp
+        u_l = phi_l = None
+        self.last_info = []
+        for lvl in range(len(self.levels) - 1, -1, -1):
+            cp, fr, ft = self.levels[lvl]
+            s, mass = emd_decompose(cp, *data[lvl])
+            warm = u_l is not None
+            u_c = u_l if warm else cp.empty(2)
+            phi_c = phi_l if warm else cp.empty()
+            _, phi_c, u_c, info = emd_pdhg_solve(cp, s, phi=phi_c, u=u_c, warm_start=warm, mass=mass)
+            self.last_info.append(info)
+            finer = self.fine if lvl == 0 else self.levels[lvl - 1][0]
+            if lvl == 0:
+                prolong(cp, finer, fr, ft, u_c, phi_c, u, phi)
+            else:
+                u_l, phi_l = prolong(cp, finer, fr, ft, u_c, phi_c)
+        return u, phi
+
+    def solve(self, pcal, pobs, emd_out=None, info_out=None):
+        """decompose -> coarse levels -> fine solve warm-started from them.
+        Returns (emd, phi, u, info, mass) of the fine plan."""
+        s, mass = emd_decompose(self.fine, pcal, pobs)
+        u, phi = self.fine.empty(2), self.fine.empty()
+        self.start(pcal, pobs, u, phi)
+        emd, phi, u, info = emd_pdhg_solve(self.fine, s, phi=phi, u=u, warm_start=True, mass=mass,
+                                           emd_out=emd_out, info_out=info_out)
+        return emd, phi, u, info, mass
+
+
 def info_numpy(info: torch.Tensor) -> np.ndarray:
     """Per-gather emd_solve_info records as a numpy structured array."""
     return np.frombuffer(info.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
@@ -337,15 +436,22 @@ class EMDMisfit(torch.autograd.Function):
     to the observed data."""
 
     @staticmethod
-    def forward(ctx, pcal, pobs, plan: Plan, warm: WarmStart | None = None):
+    def forward(ctx, pcal, pobs, plan: Plan, warm: WarmStart | None = None,
+                multigrid: "Multigrid | None" = None):
         s, mass = emd_decompose(plan, pcal, pobs)
-        if warm is None:
+        if warm is None and multigrid is None:
             emd, phi, _, info = emd_pdhg_solve(plan, s, mass=mass)
         else:
-            emd, phi, _, info = emd_pdhg_solve(plan, s, phi=warm.phi, u=warm.u, warm_start=warm.valid,
-                                               mass=mass)
-            warm.valid = True
-            phi = phi.clone()  # the state moves on with the next evaluation
+            u0 = warm.u if warm is not None else plan.empty(2)
+            phi0 = warm.phi if warm is not None else plan.empty()
+            started = warm is not None and warm.valid
+            if not started and multigrid is not None:
+                multigrid.start(pcal, pobs, u0, phi0)
+                started = True
+            emd, phi, _, info = emd_pdhg_solve(plan, s, phi=phi0, u=u0, warm_start=started, mass=mass)
+            if warm is not None:
+                warm.valid = True
+                phi = phi.clone()  # the state moves on with the next evaluation
         ctx.plan = plan
         ctx.info = info
         ctx.save_for_backward(phi, pcal, pobs, mass)
@@ -355,10 +461,12 @@ class EMDMisfit(torch.autograd.Function):
     def backward(ctx, grad_out):
         phi, pcal, pobs, mass = ctx.saved_tensors
         psi = emd_adjoint_source(ctx.plan, phi, pcal, pobs, mass, gbar=grad_out)
-        return psi, None, None, None
+        return psi, None, None, None, None
 
 
-def emd_misfit(pcal, pobs, plan: Plan, warm: WarmStart | None = None):
+def emd_misfit(pcal, pobs, plan: Plan, warm: WarmStart | None = None,
+               multigrid: Multigrid | None = None):
     """EMD of every gather of the batch, differentiable with respect to pcal.  With a
-    WarmStart, the solve starts from the previous evaluation's flux and potential."""
-    return EMDMisfit.apply(pcal, pobs, plan, warm)
+    WarmStart, the solve starts from the previous evaluation's flux and potential;
+    with a Multigrid (and no previous evaluation), from its coarse solution."""
+    return EMDMisfit.apply(pcal, pobs, plan, warm, multigrid)

@@ -1100,6 +1100,112 @@ emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, co
     return EMD_SUCCESS;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The two plans hold the same gathers, the coarse one grouped fr receivers by ft
+// samples; returns the largest per-gather cell count of the side the kernel walks.
+emd_status check_transfer(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft,
+                          bool walk_fine, int64_t& max_cells)
+{
+    if (!fine || !coarse) return fail(EMD_ERR_NULL_POINTER, "fine and coarse plans are required");
+    if (fr < 1 || ft < 1) return fail(EMD_ERR_INVALID_ARGUMENT, "fr and ft must be >= 1");
+    if (fine->ngather != coarse->ngather)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "the plans hold different numbers of gathers");
+    if (fine->params.precision != coarse->params.precision)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "the plans have different precisions");
+    if (fine->device != coarse->device) return fail(EMD_ERR_DEVICE, "the plans are on different devices");
+    if (fine->ngather > 65535) return fail(EMD_ERR_UNSUPPORTED, "grid transfer takes at most 65535 gathers");
+    max_cells = 0;
+    for (int g = 0; g < fine->ngather; ++g) {
+        const emd_gather_desc& f = fine->desc[g];
+        const emd_gather_desc& c = coarse->desc[g];
+        if (c.nr != (f.nr + fr - 1) / fr || c.nt != (f.nt + ft - 1) / ft)
+            return fail(EMD_ERR_INVALID_ARGUMENT,
+                        "gather " + std::to_string(g) + ": the coarse grid must be ceil(nr / fr) x ceil(nt / ft)");
+        max_cells = std::max(max_cells, walk_fine ? (int64_t)f.nr * f.nt : (int64_t)c.nr * c.nt);
+    }
+    return check_device(const_cast<emd_plan*>(fine));
+}
+
+int transfer_blocks(int64_t cells) { return (int)std::min<int64_t>((cells + 255) / 256, 2048); }
+
+template <typename T>
+XferArgs<T> xfer_args(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft)
+{
+    XferArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.meta_f = fine->d_meta;
+    a.meta_c = coarse->d_meta;
+    a.fr = fr;
+    a.ft = ft;
+    a.len_f = fine->batch_len;
+    a.len_c = coarse->batch_len;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+emd_status emd_restrict(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft,
+                        const void* fine_in, void* coarse_out, hipStream_t stream)
+{
+    g_last_error.clear();
+    const Range range("emd_restrict");
+    int64_t cells = 0;
+    emd_status st = check_transfer(fine, coarse, fr, ft, false, cells);
+    if (st != EMD_SUCCESS) return st;
+    if (!fine_in || !coarse_out) return fail(EMD_ERR_NULL_POINTER, "fine_in and coarse_out are required");
+    if (fine_in == coarse_out) return fail(EMD_ERR_INVALID_ARGUMENT, "coarse_out aliases fine_in");
+    if (fine->params.precision == EMD_F32) {
+        XferArgs<float> a = xfer_args<float>(fine, coarse, fr, ft);
+        a.in = static_cast<const float*>(fine_in);
+        a.out = static_cast<float*>(coarse_out);
+        launch_restrict<float>(a, fine->ngather, transfer_blocks(cells), stream);
+    } else {
+        XferArgs<double> a = xfer_args<double>(fine, coarse, fr, ft);
+        a.in = static_cast<const double*>(fine_in);
+        a.out = static_cast<double*>(coarse_out);
+        launch_restrict<double>(a, fine->ngather, transfer_blocks(cells), stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
+emd_status emd_prolong(const emd_plan* coarse, const emd_plan* fine, int32_t fr, int32_t ft,
+                       const void* u_c, const void* phi_c, void* u_f, void* phi_f, hipStream_t stream)
+{
+    g_last_error.clear();
+    const Range range("emd_prolong");
+    int64_t cells = 0;
+    emd_status st = check_transfer(fine, coarse, fr, ft, true, cells);
+    if (st != EMD_SUCCESS) return st;
+    if (!u_f && !phi_f) return fail(EMD_ERR_NULL_POINTER, "u_f or phi_f is required");
+    if ((u_f && !u_c) || (phi_f && !phi_c))
+        return fail(EMD_ERR_NULL_POINTER, "each fine output needs its coarse input");
+    if ((u_f && (u_f == u_c || u_f == phi_c)) || (phi_f && (phi_f == u_c || phi_f == phi_c)))
+        return fail(EMD_ERR_INVALID_ARGUMENT, "a fine output aliases a coarse input");
+    if (fine->params.precision == EMD_F32) {
+        XferArgs<float> a = xfer_args<float>(fine, coarse, fr, ft);
+        a.u_c = static_cast<const float*>(u_c);
+        a.phi_c = static_cast<const float*>(phi_c);
+        a.u_f = static_cast<float*>(u_f);
+        a.phi_f = static_cast<float*>(phi_f);
+        launch_prolong<float>(a, fine->ngather, transfer_blocks(cells), stream);
+    } else {
+        XferArgs<double> a = xfer_args<double>(fine, coarse, fr, ft);
+        a.u_c = static_cast<const double*>(u_c);
+        a.phi_c = static_cast<const double*>(phi_c);
+        a.u_f = static_cast<double*>(u_f);
+        a.phi_f = static_cast<double*>(phi_f);
+        launch_prolong<double>(a, fine->ngather, transfer_blocks(cells), stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
 const char* emd_status_string(emd_status status)
 {
     switch (status) {

@@ -420,6 +420,109 @@ __global__ __launch_bounds__(256) void k_lsd_apply(AuxArgs<T> a)
     write_record(a.part, tv.slot, acc);
 }
 
+// ------------------------------------------------------------------ grid transfer
+//
+// The multi-grid strategy: the EMD is first computed on a coarse grid, then the
+// primal-dual method runs on the fine grid from the coarse solution.  The coarse
+// grid groups fr receivers by ft samples, with spacings fr dx and ft dt, so the flux
+// and the potential keep their scale between the grids.
+
+// Restriction: coarse cell (I, J) = mean of the fine cells of its block (the last
+// block of a row or column holds what is left).  One thread per coarse cell.
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(XferArgs<T> a)
+{
+    const int g = blockIdx.y;
+    const GatherMeta f = a.meta_f[g], c = a.meta_c[g];
+    const int64_t ncell = (int64_t)c.nr * c.nt;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int I = (int)(idx / c.nt), J = (int)(idx % c.nt);
+        const int i1 = min(a.fr * I + a.fr, f.nr), j1 = min(a.ft * J + a.ft, f.nt);
+        double sum = 0.0;
+        int count = 0;
+        for (int i = a.fr * I; i < i1; ++i)
+            for (int j = a.ft * J; j < j1; ++j) {
+                sum += double(a.in[f.uoff + (int64_t)i * f.nt + j]);
+                ++count;
+            }
+        a.out[c.uoff + idx] = T(sum / count);
+    }
+}
+
+// Where fine index i falls between the coarse samples of one axis: samples k0, k1
+// with weights w0, w1; k < 0 stands for a zero sample.  Cell-centred samples: the
+// fine cell sits at coarse coordinate (i - (f - 1)/2) / f, clamped to [0, n - 1].
+// Edge samples (a flux component along its own axis; edge k lies between cells
+// k - 1 and k): fine edge i sits at i / f on the coarse edges 0..n, whose two ends
+// are boundary edges carrying no flux.
+struct AxisW {
+    int k0, k1;
+    double w0, w1;
+};
+
+__device__ __forceinline__ AxisW axis_w(int i, int f, int n, bool edge)
+{
+    const int hi = edge ? n : n - 1;
+    double x = edge ? double(i) / f : (i - 0.5 * (f - 1)) / f;
+    x = fmin(fmax(x, 0.0), double(hi));
+    AxisW w;
+    if (hi <= 0) {
+        w.k0 = 0;
+        w.k1 = 0;
+        w.w0 = 1.0;
+        w.w1 = 0.0;
+    } else {
+        int k = (int)floor(x);
+        if (k >= hi) k = hi - 1;
+        w.k0 = k;
+        w.k1 = k + 1;
+        w.w1 = x - k;
+        w.w0 = 1.0 - w.w1;
+    }
+    if (edge) {
+        if (w.k0 == 0 || w.k0 == n) w.k0 = -1;
+        if (w.k1 == 0 || w.k1 == n) w.k1 = -1;
+    }
+    return w;
+}
+
+template <typename T>
+__device__ __forceinline__ double csample(const T* v, const GatherMeta& c, int a, int b)
+{
+    return (a < 0 || b < 0) ? 0.0 : double(v[c.uoff + (int64_t)a * c.nt + b]);
+}
+
+template <typename T>
+__device__ __forceinline__ double blend(const T* v, const GatherMeta& c, const AxisW& r, const AxisW& t)
+{
+    return r.w0 * t.w0 * csample(v, c, r.k0, t.k0) + r.w0 * t.w1 * csample(v, c, r.k0, t.k1) +
+           r.w1 * t.w0 * csample(v, c, r.k1, t.k0) + r.w1 * t.w1 * csample(v, c, r.k1, t.k1);
+}
+
+// Prolongation: bilinear interpolation of the coarse u^x (receiver edges, time
+// centres), u^t (time edges, receiver centres) and phi (centres) onto the fine
+// grid.  One thread per fine cell.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(XferArgs<T> a)
+{
+    const int g = blockIdx.y;
+    const GatherMeta f = a.meta_f[g], c = a.meta_c[g];
+    const int64_t ncell = (int64_t)f.nr * f.nt;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / f.nt), j = (int)(idx % f.nt);
+        const AxisW rc = axis_w(i, a.fr, c.nr, false), re = axis_w(i, a.fr, c.nr, true);
+        const AxisW tc = axis_w(j, a.ft, c.nt, false), te = axis_w(j, a.ft, c.nt, true);
+        const int64_t o = f.uoff + idx;
+        if (a.u_f) {
+            a.u_f[o] = T(blend(a.u_c, c, re, tc));
+            a.u_f[a.len_f + o] = T(blend(a.u_c + a.len_c, c, rc, te));
+        }
+        if (a.phi_f) a.phi_f[o] = T(blend(a.phi_c, c, rc, tc));
+    }
+}
+
 // value[g] = 1/2 dx dt sum (Pcal - Pobs)^2
 template <typename T>
 __global__ __launch_bounds__(64) void k_lsd_value(AuxArgs<T> a)
@@ -480,6 +583,18 @@ void launch_adjoint(const AuxArgs<T>& a, int grid, hipStream_t stream)
     hipLaunchKernelGGL(k_adj_apply<T>, dim3(grid), dim3(256), 0, stream, a);
 }
 
+template <typename T>
+void launch_restrict(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks, ngather), dim3(256), 0, stream, a);
+}
+
+template <typename T>
+void launch_prolong(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_prolong<T>, dim3(blocks, ngather), dim3(256), 0, stream, a);
+}
+
 void launch_zero_counter(int32_t* counter, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
@@ -492,7 +607,9 @@ void launch_zero_counter(int32_t* counter, hipStream_t stream)
     template void launch_finalize<T>(const AuxArgs<T>&, hipStream_t);               \
     template void launch_decompose<T>(const AuxArgs<T>&, int, hipStream_t);         \
     template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);           \
-    template void launch_lsd<T>(const AuxArgs<T>&, int, hipStream_t);
+    template void launch_lsd<T>(const AuxArgs<T>&, int, hipStream_t);                \
+    template void launch_restrict<T>(const XferArgs<T>&, int, int, hipStream_t);     \
+    template void launch_prolong<T>(const XferArgs<T>&, int, int, hipStream_t);
 EMD_INST(float)
 EMD_INST(double)
 #undef EMD_INST

@@ -65,7 +65,25 @@ struct AuxArgs {
     double eps, delta_unused, alpha_max_factor;
 };
 
+// Grid transfer between a fine plan and a coarse plan of the same gathers, grouped
+// fr receivers by ft samples (caller's batch layout on both sides).
+template <typename T>
+struct XferArgs {
+    const GatherMeta* meta_f;  // fine plan's gathers
+    const GatherMeta* meta_c;  // coarse plan's gathers (same order)
+    int32_t fr, ft;
+    int64_t len_f, len_c;      // batch lengths (offset of u^t after u^x)
+    const T* in;               // restriction: fine field
+    T* out;                    // restriction: coarse field
+    const T* u_c;              // prolongation: coarse [u^x | u^t] or NULL
+    const T* phi_c;            //   coarse phi or NULL
+    T* u_f;                    //   fine [u^x | u^t] or NULL
+    T* phi_f;                  //   fine phi or NULL
+};
+
 template <typename T> void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream);
+template <typename T> void launch_restrict(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream);
+template <typename T> void launch_prolong(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream);
 template <typename T> void launch_copy_in(const AuxArgs<T>& a, int warm, int grid, hipStream_t stream);
 template <typename T> void launch_gather_init(const AuxArgs<T>& a, hipStream_t stream);
 template <typename T> void launch_copy_out(const AuxArgs<T>& a, int grid, hipStream_t stream);

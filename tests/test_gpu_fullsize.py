@@ -369,6 +369,47 @@ def test_l1_linesearch_to_the_stop_rule_at_full_size():
     assert rel.max() <= 1e-4
 
 
+def test_coarse_to_fine_solve_of_full_size_gathers():
+    # two gathers of the 16 x 4000 x 1600 workload: solved on a grid 4x coarser in
+    # time first, the fine solve needs far fewer iterations and reaches the same EMD
+    # (to the accuracy of the 1e-5 stop rule, certified by the duality bracket)
+    c5 = config5_batch()
+    gs = [c5[12], c5[1]]
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=1000000)
+    log(f"2 gathers {gs[0].nr}x{gs[0].nt}, cold and coarse-to-fine (1 x 4), to 1e-5")
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    emd_c, _, _, info_c = E.emd_pdhg_solve(plan, s, u=plan.empty(2), mass=mass)
+    ev[1].record()
+    mg = E.Multigrid(plan, ((1, 4),))
+    ev[2].record()
+    emd_w, phi_w, u_w, info_w, _ = mg.solve(pcal, pobs)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ic, iw = E.info_numpy(info_c), E.info_numpy(info_w)
+    ik = E.info_numpy(mg.last_info[0])
+    log(f"  cold: {ic['iters'].tolist()} iterations, {ev[0].elapsed_time(ev[1]) / 1e3:.2f} s; "
+        f"coarse {ik['iters'].tolist()} + fine {iw['iters'].tolist()}, "
+        f"{ev[2].elapsed_time(ev[3]) / 1e3:.2f} s")
+    assert np.all(iw["status"] == E.GATHER_STATUS.index("CONVERGED"))
+    assert np.all(iw["iters"] < 0.6 * ic["iters"])
+    np.testing.assert_allclose(emd_w.cpu().numpy(), emd_c.cpu().numpy(), rtol=1e-4)
+    # the warm-started solve stops with a smoother residual, whose transport costs
+    # more: its bracket is wider on the upper side (2.8e-3 for the first gather)
+    us, phis = unpack(u_w.cpu().numpy(), desc, 2), unpack(phi_w.cpu().numpy(), desc)
+    for k, g in enumerate(gs):
+        sk, _, _, _ = oracle.decompose(g.pcal, g.pobs, g.dx, g.dt)
+        lo, w, hi = transport_bounds(sk, us[k][0], us[k][1], phis[k], g.dx, g.dt)
+        log(f"  gather {k}: bracket gap {(hi - lo) / hi:.2e}, transport above the lower bound "
+            f"by {(w - lo) / w:.2e}")
+        assert lo - (hi - w) <= w <= hi and (hi - lo) / hi <= 5e-3 and (w - lo) / w <= 1e-3
+        assert lo <= float(emd_c[k]) * (1 + 1e-3)
+    mg.close()
+    plan.close()
+
+
 def test_large_batch_fixed_budget():
     # 16 gathers of 4000 x 1600 (102 M cells, 3.7 GB of solver state): a fixed
     # budget, then the oracle's recomputation on sampled gathers
