@@ -9,6 +9,7 @@ current stream of the tensors' device.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import hashlib
 import json
 import os
@@ -357,15 +358,21 @@ class Multigrid:
     the coarsest level is solved cold, and each solution, prolonged bilinearly
     (u and phi), starts the solve of the next finer level; the fine solve itself is
     left to the caller, who warm-starts it from (u, phi) written by start().  The
-    coarse plans are built once, with the fine plan's parameters unless given."""
+    coarse plans are built once, with the fine plan's parameters unless given; a
+    coarse level never uses mass mode `none` (block means over the ragged last
+    blocks shift the two masses slightly, and a coarse level only supplies a start),
+    it balances the masses instead."""
 
     def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None):
         self.fine = plan
         self.levels = []  # (coarse plan, fr, ft), finest first
+        prm = params or plan.params
+        if prm.mass_mode == L.MASS_NONE:
+            prm = dataclasses.replace(prm, mass_mode=L.MASS_BALANCE)
         descs = plan.descs
         for fr, ft in factors:
             cd, n = coarse_descs(descs, int(fr), int(ft))
-            self.levels.append((Plan(cd, n, params or plan.params, device=plan.device), int(fr), int(ft)))
+            self.levels.append((Plan(cd, n, prm, device=plan.device), int(fr), int(ft)))
             descs = cd
         self.last_info = []  # per level, coarsest first: the solve info of the last start()
 

@@ -172,3 +172,26 @@ def test_multigrid_through_autograd():
     assert torch.isfinite(x.grad).all() and x.grad.abs().sum() > 0
     mg.close()
     plan.close()
+
+
+def test_multigrid_with_mass_mode_none():
+    # the fine problem as printed (no mass balancing, masses equal by construction);
+    # the coarse level balances its block means and still supplies a usable start
+    gs = to_precision([config2_gather(nr=20, nt=301, f_peak=4.0, dtype=np.float64)], np.float32)
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=100000, mass_mode=E.MASS_NONE,
+                       mass_tol=1e-3)
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    mg = E.Multigrid(plan, ((1, 4),))
+    assert mg.levels[0][0].params.mass_mode == E.MASS_BALANCE
+    emd_w, _, _, info_w, _ = mg.solve(pcal, pobs)
+    s, mass = E.emd_decompose(plan, pcal, pobs)
+    emd_c, _, _, info_c = E.emd_pdhg_solve(plan, s, mass=mass)
+    torch.cuda.synchronize()
+    iw, ic = E.info_numpy(info_w), E.info_numpy(info_c)
+    log(f"  mass mode none: statuses {iw['status'].tolist()} / {ic['status'].tolist()}, "
+        f"fine iterations {iw['iters'].tolist()} (cold {ic['iters'].tolist()})")
+    np.testing.assert_array_equal(iw["status"], ic["status"])
+    if ic["status"][0] == E.GATHER_STATUS.index("CONVERGED"):
+        np.testing.assert_allclose(emd_w.cpu().numpy(), emd_c.cpu().numpy(), rtol=2e-4)
+    mg.close()
+    plan.close()
