@@ -119,8 +119,9 @@ def main():
     ap.add_argument("--f64-gathers", type=int, default=2,
                     help="gathers of the workload solved by the plain FP64 path (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--multigrid", default="1x2", metavar="FRxFT[,FRxFT...]",
-                    help="also time the coarse-to-fine solve with these level factors ('none': skip)")
+    ap.add_argument("--multigrid", default="auto", metavar="FRxFT[,FRxFT...]",
+                    help="also time the coarse-to-fine solve with these level factors ('none': skip; "
+                         "'auto': the measured best for the workload, 1x4,2x4 for c5, else 1x2)")
     ap.add_argument("--mg-steps", type=int, default=1, help="timed coarse-to-fine steps")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -300,6 +301,8 @@ def main():
         cpu = cpu_baseline(gathers, args.cpu_iters, threads)
         log(f"cpu oracle: {cpu['value']:.3e} cell-updates/s on {threads} threads")
 
+    if args.multigrid == "auto":
+        args.multigrid = "1x4,2x4" if args.workload == "c5" else "1x2"
     if args.multigrid != "none" and args.mg_steps > 0:
         # the same step (decompose, solve, adjoint source) with the solve started from
         # coarser grids; the headline metric stays the plain solve's
