@@ -101,3 +101,46 @@ def test_time_weighting_moves_transport_to_the_receiver_axis():
     e = emd.cpu().numpy()
     assert e[0] < e[1] < e[2]
     plan.close()
+
+
+def test_two_plans_on_two_streams_from_two_threads():
+    # shots handled as separate plans, each on its own stream and host thread (the
+    # plans share no state; a call releases the interpreter while it runs): the
+    # concurrent solves give bitwise the results of solving the plans one after the
+    # other
+    import threading
+    from synth import random_small_pair
+    sets = [[config2_gather(seed=31, nr=40, nt=300, f_peak=3.0), random_small_pair(9, 120, 32)],
+            [config2_gather(seed=33, nr=30, nt=400, f_peak=3.0), random_small_pair(5, 77, 34)]]
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=200000)
+    plans = [make_plan(gs, p) for gs in sets]
+
+    def solve(k, out, stream=None):
+        plan, pcal, pobs, _ = plans[k]
+        ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream())
+        with ctx:
+            s, mass = E.emd_decompose(plan, pcal, pobs)
+            emd, phi, u, info = E.emd_pdhg_solve(plan, s, u=plan.empty(2), mass=mass)
+            torch.cuda.current_stream().synchronize()
+            out[k] = (emd.cpu().numpy(), phi.cpu().numpy(), u.cpu().numpy(), E.info_numpy(info))
+
+    seq = {}
+    for k in range(2):
+        solve(k, seq)
+    torch.cuda.synchronize()
+    par = {}
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    threads = [threading.Thread(target=solve, args=(k, par, streams[k])) for k in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+        assert not th.is_alive()
+    torch.cuda.synchronize()
+    for k in range(2):
+        for a, b in zip(seq[k][:3], par[k][:3]):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(seq[k][3], par[k][3])
+    log(f"  iterations {[seq[k][3]['iters'].tolist() for k in range(2)]}")
+    for plan, *_ in plans:
+        plan.close()
