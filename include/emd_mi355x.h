@@ -191,10 +191,9 @@ emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows);
  * runs after a warm-up), and keeps a height when it is faster by more than 0.3 %.
  * (Taller tiles are not tried: they lengthen each launch of the last few running
  * gathers, which a whole-batch timing does not see.)  The chosen heights stay in
- * the plan (read them
- * with emd_plan_get_gather_tiling to reuse them).  The plan's parameters are left
- * unchanged; its workspace is overwritten; synchronises the device.  Timing-based,
- * so the choice can differ from run to run. */
+ * the plan (read them with emd_plan_get_gather_tiling to reuse them).  The plan's
+ * parameters are left unchanged; its workspace is overwritten; synchronises the
+ * device.  Timing-based, so the choice can differ from run to run. */
 emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipStream_t stream);
 
 /* Fill *out with the plan's sizes and the counters of its last solve. */
