@@ -106,7 +106,8 @@ typedef struct {
  *   mass_mode: how emd_decompose builds s (see there) and emd_adjoint_source chains.
  *   precision: element type of all field buffers (EMD_F32: float fields, FP64
  *     reductions and scalars; EMD_F64: double throughout).
- *   sweeps_per_sync: iterations enqueued between reads of the finished count. */
+ *   sweeps_per_sync: iterations enqueued between reads of the finished count
+ *     (even, 2..4096). */
 typedef struct {
     double eps, xi, zeta, delta, alpha1, alpha_max_factor, tol_res, mass_tol;
     int32_t max_iter, check_every, max_ls_trials, ls_mode;
@@ -167,7 +168,8 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
 /* Release the plan and its workspace (synchronises the device first). NULL is a no-op. */
 emd_status emd_plan_destroy(emd_plan* plan);
 
-/* Replace the solver parameters of an existing plan (precision must not change). */
+/* Replace the solver parameters of an existing plan (precision must not change).
+ * Synchronises the device. */
 emd_status emd_plan_set_params(emd_plan* plan, const emd_params* p);
 
 /* Choose the tile height (receiver rows per wavefront tile, 1..1024) of every
@@ -222,7 +224,8 @@ emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, voi
  *   d_mass: optional device double[3 ngather] from emd_decompose; with
  *      EMD_MASS_NONE it flags gathers whose masses differ (MASS_IMBALANCE).
  *   d_emd: optional device double[ngather] receiving the EMD values.
- *   d_info: optional device emd_solve_info[ngather]. */
+ *   d_info: optional device emd_solve_info[ngather].
+ * s must not alias u or phi (the same holds for the resume and replay forms). */
 emd_status emd_pdhg_solve(emd_plan* plan, const void* s, void* u, void* phi, int32_t warm_start,
                           const double* d_mass, double* d_emd, emd_solve_info* d_info,
                           hipStream_t stream);

@@ -134,8 +134,10 @@ emd_status validate_params(const emd_params* p)
     if (p->ls_mode < EMD_LS_L2 || p->ls_mode > EMD_LS_FIXED) return bad("unknown ls_mode");
     if (p->mass_mode < EMD_MASS_BALANCE || p->mass_mode > EMD_MASS_NONE) return bad("unknown mass_mode");
     if (p->precision != EMD_F32 && p->precision != EMD_F64) return bad("unknown precision");
-    if (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096)
-        return bad("sweeps_per_sync must lie in [2, 4096]");
+    // a solve reads the newest state from buffer 0, so every chunk is an even number
+    // of sweeps
+    if (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096 || (p->sweeps_per_sync & 1))
+        return bad("sweeps_per_sync must be even and lie in [2, 4096]");
     return EMD_SUCCESS;
 }
 
@@ -734,6 +736,7 @@ emd_status emd_plan_set_params(emd_plan* plan, const emd_params* p)
         return fail(EMD_ERR_INVALID_ARGUMENT, "precision cannot change on an existing plan");
     st = check_device(plan);
     if (st != EMD_SUCCESS) return st;
+    HIP_TRY(hipDeviceSynchronize());  // enqueued work may still read the gather table
     plan->params = *p;
     return build_tiles(plan);  // alpha_1 depends on delta and alpha1
 }
@@ -968,6 +971,7 @@ emd_status emd_pdhg_solve_replay(emd_plan* plan, const void* s, void* u, void* p
     const Range range("emd_pdhg_solve_replay");
     if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
     if (!s || !phi || !d_alpha) return fail(EMD_ERR_NULL_POINTER, "s, phi and d_alpha are required");
+    if (s == phi || s == u) return fail(EMD_ERR_INVALID_ARGUMENT, "s aliases an output");
     if (ld_alpha < plan->params.max_iter)
         return fail(EMD_ERR_INVALID_ARGUMENT, "ld_alpha must be >= max_iter");
     emd_status st = check_device(plan);
