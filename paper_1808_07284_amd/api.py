@@ -201,6 +201,35 @@ class Plan:
             raise ValueError(f"{name}: expected {lead + (self.batch_len,)} elements")
 
 
+def _check_buf(plan: Plan, t, name: str, dtype: torch.dtype, numel: int):
+    """A per-gather buffer the kernels read or write (masses, EMD values, solve info,
+    step schedules): a contiguous tensor of `dtype` on the plan's device holding at
+    least `numel` elements (None passes: the argument is optional)."""
+    if t is None:
+        return
+    if t.device != plan.device or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor on {plan.device}, "
+                         f"got {t.dtype} on {t.device}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: expected at least {numel} elements, got {t.numel()}")
+
+
+def _check_outputs(plan: Plan, mass, emd_out, info_out):
+    _check_buf(plan, mass, "mass", torch.float64, 3 * plan.ngather)
+    _check_buf(plan, emd_out, "emd_out", torch.float64, plan.ngather)
+    _check_buf(plan, info_out, "info_out", torch.uint8, plan.ngather * INFO_DTYPE.itemsize)
+
+
+def _gbar(plan: Plan, gbar):
+    """Upstream gradients per gather as a float64 device vector (None: all 1)."""
+    if gbar is None:
+        return None
+    gbar = gbar.to(device=plan.device, dtype=torch.float64).contiguous()
+    if gbar.numel() != plan.ngather:
+        raise ValueError(f"gbar: expected {plan.ngather} values, got {gbar.numel()}")
+    return gbar
+
+
 def emd_decompose(plan: Plan, pcal, pobs, s_out=None, f_out=None, g_out=None, mass_out=None):
     """Mainini recombination and mass normalisation (Section 2.1).
     Returns (s, mass) with mass[g] = (M_f, M_g, mean(Pcal - Pobs))."""
@@ -209,6 +238,7 @@ def emd_decompose(plan: Plan, pcal, pobs, s_out=None, f_out=None, g_out=None, ma
                 if mass_out is None else mass_out)
     for t, n in ((pcal, "pcal"), (pobs, "pobs"), (s_out, "s_out"), (f_out, "f_out"), (g_out, "g_out")):
         plan._check(t, n)
+    _check_buf(plan, mass_out, "mass_out", torch.float64, 3 * plan.ngather)
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_decompose(plan.handle, _ptr(pcal), _ptr(pobs), _ptr(s_out), _ptr(f_out),
                                        _ptr(g_out), _ptr(mass_out), _stream(plan.device)))
@@ -227,6 +257,7 @@ def emd_pdhg_solve(plan: Plan, s, phi=None, u=None, warm_start=False, mass=None,
     plan._check(s, "s")
     plan._check(phi, "phi")
     plan._check(u, "u", (2,))
+    _check_outputs(plan, mass, emd_out, info_out)
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_pdhg_solve(plan.handle, _ptr(s), _ptr(u), _ptr(phi), int(bool(warm_start)),
                                         _ptr(mass), _ptr(emd_out), _ptr(info_out),
@@ -245,9 +276,11 @@ def emd_pdhg_solve_replay(plan: Plan, s, alpha, phi=None, u=None, warm_start=Fal
     if alpha.dtype != torch.float64 or alpha.dim() != 2 or alpha.shape[0] != plan.ngather:
         raise ValueError("alpha must be a float64 [ngather, ld] tensor")
     alpha = alpha.contiguous()
+    _check_buf(plan, alpha, "alpha", torch.float64, alpha.numel())
     plan._check(s, "s")
     plan._check(phi, "phi")
     plan._check(u, "u", (2,))
+    _check_outputs(plan, None, emd_out, info_out)
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_pdhg_solve_replay(plan.handle, _ptr(s), _ptr(u), _ptr(phi),
                                                int(bool(warm_start)), _ptr(alpha),
@@ -275,6 +308,9 @@ def emd_pdhg_solve_resume(plan: Plan, s, state, u, phi, mass=None, emd_out=None,
     plan._check(s, "s")
     plan._check(phi, "phi")
     plan._check(u, "u", (2,))
+    _check_outputs(plan, mass, emd_out, info_out)
+    if len(state) != plan.ngather:
+        raise ValueError(f"state: expected {plan.ngather} gather states, got {len(state)}")
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_pdhg_solve_resume(plan.handle, _ptr(s), _ptr(u), _ptr(phi), state, _ptr(mass),
                                                _ptr(emd_out), _ptr(info_out), _stream(plan.device)))
@@ -286,8 +322,8 @@ def emd_adjoint_source(plan: Plan, phi, pcal=None, pobs=None, mass=None, gbar=No
     psi_out = plan.empty() if psi_out is None else psi_out
     for t, n in ((phi, "phi"), (pcal, "pcal"), (pobs, "pobs"), (psi_out, "psi_out")):
         plan._check(t, n)
-    if gbar is not None:
-        gbar = gbar.to(device=plan.device, dtype=torch.float64).contiguous()
+    _check_buf(plan, mass, "mass", torch.float64, 3 * plan.ngather)
+    gbar = _gbar(plan, gbar)
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_adjoint_source(plan.handle, _ptr(phi), _ptr(pcal), _ptr(pobs), _ptr(mass),
                                             _ptr(gbar), _ptr(psi_out), _stream(plan.device)))
@@ -304,8 +340,8 @@ def lsd_misfit(plan: Plan, pcal, pobs, gbar=None, value_out=None, psi_out=None, 
         plan._check(t, n)
     value_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
                  if value_out is None else value_out)
-    if gbar is not None:
-        gbar = gbar.to(device=plan.device, dtype=torch.float64).contiguous()
+    _check_buf(plan, value_out, "value_out", torch.float64, plan.ngather)
+    gbar = _gbar(plan, gbar)
     with torch.cuda.device(plan.device):
         L.check(L.load().emd_lsd_misfit(plan.handle, _ptr(pcal), _ptr(pobs), _ptr(gbar), _ptr(value_out),
                                         _ptr(psi_out), _stream(plan.device)))

@@ -1,0 +1,51 @@
+"""Host-side argument checks of the Python binding: every per-gather buffer handed to
+a kernel (masses, EMD values, solve records, step schedules, upstream gradients) must
+be a contiguous tensor of the expected type on the plan's device and large enough,
+or the binding raises before anything reaches the library."""
+from types import SimpleNamespace
+
+import pytest
+import torch
+
+import paper_1808_07284_amd.api as A
+
+
+def _plan(device="cpu", ngather=3):
+    return SimpleNamespace(device=torch.device(device), ngather=ngather)
+
+
+def test_buffer_on_another_device_is_rejected():
+    plan = _plan("cuda")
+    with pytest.raises(ValueError, match="mass"):
+        A._check_buf(plan, torch.zeros(9, dtype=torch.float64), "mass", torch.float64, 9)
+
+
+def test_buffer_type_size_and_layout():
+    plan = _plan()
+    A._check_buf(plan, None, "emd_out", torch.float64, 3)  # optional
+    A._check_buf(plan, torch.zeros(3, 3, dtype=torch.float64), "mass", torch.float64, 9)
+    with pytest.raises(ValueError, match="float64"):
+        A._check_buf(plan, torch.zeros(9, dtype=torch.float32), "mass", torch.float64, 9)
+    with pytest.raises(ValueError, match="at least 9"):
+        A._check_buf(plan, torch.zeros(8, dtype=torch.float64), "mass", torch.float64, 9)
+    with pytest.raises(ValueError, match="contiguous"):
+        A._check_buf(plan, torch.zeros(3, 6, dtype=torch.float64)[:, ::2], "mass", torch.float64, 9)
+
+
+def test_solve_outputs():
+    plan = _plan()
+    ok_info = torch.zeros(3 * A.INFO_DTYPE.itemsize, dtype=torch.uint8)
+    A._check_outputs(plan, torch.zeros(3, 3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64), ok_info)
+    with pytest.raises(ValueError, match="info_out"):
+        A._check_outputs(plan, None, None, ok_info[:-1])
+    with pytest.raises(ValueError, match="emd_out"):
+        A._check_outputs(plan, None, torch.zeros(3, dtype=torch.float32), None)
+
+
+def test_upstream_gradients_are_one_per_gather():
+    plan = _plan()
+    assert A._gbar(plan, None) is None
+    g = A._gbar(plan, torch.tensor([1.0, 2.0, 3.0], dtype=torch.float32))
+    assert g.dtype == torch.float64 and g.tolist() == [1.0, 2.0, 3.0]
+    with pytest.raises(ValueError, match="gbar"):
+        A._gbar(plan, torch.ones(2))
