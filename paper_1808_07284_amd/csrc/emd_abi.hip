@@ -1109,9 +1109,9 @@ emd_status emd_lsd_misfit(emd_plan* plan, const void* pcal, const void* pobs, co
 namespace {
 
 // The two plans hold the same gathers, the coarse one grouped fr receivers by ft
-// samples; returns the largest per-gather cell count of the side the kernel walks.
+// samples; returns the largest per-gather row count of the side the kernel walks.
 emd_status check_transfer(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft,
-                          bool walk_fine, int64_t& max_cells)
+                          bool walk_fine, int32_t& max_rows)
 {
     if (!fine || !coarse) return fail(EMD_ERR_NULL_POINTER, "fine and coarse plans are required");
     if (fr < 1 || ft < 1) return fail(EMD_ERR_INVALID_ARGUMENT, "fr and ft must be >= 1");
@@ -1121,19 +1121,20 @@ emd_status check_transfer(const emd_plan* fine, const emd_plan* coarse, int32_t 
         return fail(EMD_ERR_INVALID_ARGUMENT, "the plans have different precisions");
     if (fine->device != coarse->device) return fail(EMD_ERR_DEVICE, "the plans are on different devices");
     if (fine->ngather > 65535) return fail(EMD_ERR_UNSUPPORTED, "grid transfer takes at most 65535 gathers");
-    max_cells = 0;
+    max_rows = 0;
     for (int g = 0; g < fine->ngather; ++g) {
         const emd_gather_desc& f = fine->desc[g];
         const emd_gather_desc& c = coarse->desc[g];
         if (c.nr != (f.nr + fr - 1) / fr || c.nt != (f.nt + ft - 1) / ft)
             return fail(EMD_ERR_INVALID_ARGUMENT,
                         "gather " + std::to_string(g) + ": the coarse grid must be ceil(nr / fr) x ceil(nt / ft)");
-        max_cells = std::max(max_cells, walk_fine ? (int64_t)f.nr * f.nt : (int64_t)c.nr * c.nt);
+        max_rows = std::max(max_rows, walk_fine ? f.nr : c.nr);
     }
     return check_device(const_cast<emd_plan*>(fine));
 }
 
-int transfer_blocks(int64_t cells) { return (int)std::min<int64_t>((cells + 255) / 256, 2048); }
+// one block per row of the walked grid, at most 2048 per gather (blocks then stride)
+int transfer_blocks(int32_t rows) { return std::max(1, std::min(rows, 2048)); }
 
 template <typename T>
 XferArgs<T> xfer_args(const emd_plan* fine, const emd_plan* coarse, int32_t fr, int32_t ft)
@@ -1158,8 +1159,8 @@ emd_status emd_restrict(const emd_plan* fine, const emd_plan* coarse, int32_t fr
 {
     g_last_error.clear();
     const Range range("emd_restrict");
-    int64_t cells = 0;
-    emd_status st = check_transfer(fine, coarse, fr, ft, false, cells);
+    int32_t rows = 0;
+    emd_status st = check_transfer(fine, coarse, fr, ft, false, rows);
     if (st != EMD_SUCCESS) return st;
     if (!fine_in || !coarse_out) return fail(EMD_ERR_NULL_POINTER, "fine_in and coarse_out are required");
     if (fine_in == coarse_out) return fail(EMD_ERR_INVALID_ARGUMENT, "coarse_out aliases fine_in");
@@ -1167,12 +1168,12 @@ emd_status emd_restrict(const emd_plan* fine, const emd_plan* coarse, int32_t fr
         XferArgs<float> a = xfer_args<float>(fine, coarse, fr, ft);
         a.in = static_cast<const float*>(fine_in);
         a.out = static_cast<float*>(coarse_out);
-        launch_restrict<float>(a, fine->ngather, transfer_blocks(cells), stream);
+        launch_restrict<float>(a, fine->ngather, transfer_blocks(rows), stream);
     } else {
         XferArgs<double> a = xfer_args<double>(fine, coarse, fr, ft);
         a.in = static_cast<const double*>(fine_in);
         a.out = static_cast<double*>(coarse_out);
-        launch_restrict<double>(a, fine->ngather, transfer_blocks(cells), stream);
+        launch_restrict<double>(a, fine->ngather, transfer_blocks(rows), stream);
     }
     HIP_TRY(hipGetLastError());
     return EMD_SUCCESS;
@@ -1183,8 +1184,8 @@ emd_status emd_prolong(const emd_plan* coarse, const emd_plan* fine, int32_t fr,
 {
     g_last_error.clear();
     const Range range("emd_prolong");
-    int64_t cells = 0;
-    emd_status st = check_transfer(fine, coarse, fr, ft, true, cells);
+    int32_t rows = 0;
+    emd_status st = check_transfer(fine, coarse, fr, ft, true, rows);
     if (st != EMD_SUCCESS) return st;
     if (!u_f && !phi_f) return fail(EMD_ERR_NULL_POINTER, "u_f or phi_f is required");
     if ((u_f && !u_c) || (phi_f && !phi_c))
@@ -1197,14 +1198,14 @@ emd_status emd_prolong(const emd_plan* coarse, const emd_plan* fine, int32_t fr,
         a.phi_c = static_cast<const float*>(phi_c);
         a.u_f = static_cast<float*>(u_f);
         a.phi_f = static_cast<float*>(phi_f);
-        launch_prolong<float>(a, fine->ngather, transfer_blocks(cells), stream);
+        launch_prolong<float>(a, fine->ngather, transfer_blocks(rows), stream);
     } else {
         XferArgs<double> a = xfer_args<double>(fine, coarse, fr, ft);
         a.u_c = static_cast<const double*>(u_c);
         a.phi_c = static_cast<const double*>(phi_c);
         a.u_f = static_cast<double*>(u_f);
         a.phi_f = static_cast<double*>(phi_f);
-        launch_prolong<double>(a, fine->ngather, transfer_blocks(cells), stream);
+        launch_prolong<double>(a, fine->ngather, transfer_blocks(rows), stream);
     }
     HIP_TRY(hipGetLastError());
     return EMD_SUCCESS;

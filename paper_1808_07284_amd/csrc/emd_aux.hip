@@ -428,25 +428,29 @@ __global__ __launch_bounds__(256) void k_lsd_apply(AuxArgs<T> a)
 // and the potential keep their scale between the grids.
 
 // Restriction: coarse cell (I, J) = mean of the fine cells of its block (the last
-// block of a row or column holds what is left).  One thread per coarse cell.
+// block of a row or column holds what is left).  A block walks coarse rows, its
+// threads the samples of a row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(XferArgs<T> a)
 {
     const int g = blockIdx.y;
     const GatherMeta f = a.meta_f[g], c = a.meta_c[g];
-    const int64_t ncell = (int64_t)c.nr * c.nt;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int I = (int)(idx / c.nt), J = (int)(idx % c.nt);
-        const int i1 = min(a.fr * I + a.fr, f.nr), j1 = min(a.ft * J + a.ft, f.nt);
-        double sum = 0.0;
-        int count = 0;
-        for (int i = a.fr * I; i < i1; ++i)
-            for (int j = a.ft * J; j < j1; ++j) {
-                sum += double(a.in[f.uoff + (int64_t)i * f.nt + j]);
-                ++count;
+    for (int I = blockIdx.x; I < c.nr; I += gridDim.x) {
+        const int i0 = a.fr * I, i1 = min(i0 + a.fr, f.nr);
+        const int64_t orow = c.uoff + (int64_t)I * c.nt;
+        for (int J = threadIdx.x; J < c.nt; J += blockDim.x) {
+            const int j0 = a.ft * J, j1 = min(j0 + a.ft, f.nt);
+            double sum = 0.0;
+            int count = 0;
+            for (int i = i0; i < i1; ++i) {
+                const T* row = a.in + f.uoff + (int64_t)i * f.nt;
+                for (int j = j0; j < j1; ++j) {
+                    sum += double(row[j]);
+                    ++count;
+                }
             }
-        a.out[c.uoff + idx] = T(sum / count);
+            a.out[orow + J] = T(sum / count);
+        }
     }
 }
 
@@ -502,24 +506,25 @@ __device__ __forceinline__ double blend(const T* v, const GatherMeta& c, const A
 
 // Prolongation: bilinear interpolation of the coarse u^x (receiver edges, time
 // centres), u^t (time edges, receiver centres) and phi (centres) onto the fine
-// grid.  One thread per fine cell.
+// grid.  A block walks fine rows (the receiver weights are the row's), its threads
+// the samples of a row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(XferArgs<T> a)
 {
     const int g = blockIdx.y;
     const GatherMeta f = a.meta_f[g], c = a.meta_c[g];
-    const int64_t ncell = (int64_t)f.nr * f.nt;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(idx / f.nt), j = (int)(idx % f.nt);
+    for (int i = blockIdx.x; i < f.nr; i += gridDim.x) {
         const AxisW rc = axis_w(i, a.fr, c.nr, false), re = axis_w(i, a.fr, c.nr, true);
-        const AxisW tc = axis_w(j, a.ft, c.nt, false), te = axis_w(j, a.ft, c.nt, true);
-        const int64_t o = f.uoff + idx;
-        if (a.u_f) {
-            a.u_f[o] = T(blend(a.u_c, c, re, tc));
-            a.u_f[a.len_f + o] = T(blend(a.u_c + a.len_c, c, rc, te));
+        const int64_t orow = f.uoff + (int64_t)i * f.nt;
+        for (int j = threadIdx.x; j < f.nt; j += blockDim.x) {
+            const AxisW tc = axis_w(j, a.ft, c.nt, false), te = axis_w(j, a.ft, c.nt, true);
+            const int64_t o = orow + j;
+            if (a.u_f) {
+                a.u_f[o] = T(blend(a.u_c, c, re, tc));
+                a.u_f[a.len_f + o] = T(blend(a.u_c + a.len_c, c, rc, te));
+            }
+            if (a.phi_f) a.phi_f[o] = T(blend(a.phi_c, c, rc, tc));
         }
-        if (a.phi_f) a.phi_f[o] = T(blend(a.phi_c, c, rc, tc));
     }
 }
 
