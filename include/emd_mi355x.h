@@ -198,6 +198,18 @@ emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows);
  * device.  Timing-based, so the choice can differ from run to run. */
 emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipStream_t stream);
 
+/* Residual history: in every later solve on the plan (emd_pdhg_solve and its
+ * resume and replay forms), each gather's relative residual ||div u + s|| / ||s||
+ * at every stop-rule check (iterations c * check_every, c = 1, 2, ...; the test of
+ * Algorithm 1's stopping rule, Section 2.2) is written as a double to
+ * d_hist[g * capacity + (c - 1) % capacity]: a ring holding each gather's last
+ * `capacity` checks.  A resumed solve continues the count of its checkpoint.
+ * Entries of checks a solve does not reach are not written, and the autotuner's
+ * timing solves write none.  d_hist: caller-owned device memory of
+ * ngather * capacity doubles that must stay valid while solves on the plan may
+ * run; (NULL, 0) turns the history off (the default).  Never synchronises. */
+emd_status emd_plan_set_history(emd_plan* plan, double* d_hist, int32_t capacity);
+
 /* Fill *out with the plan's sizes and the counters of its last solve. */
 emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out);
 

@@ -28,7 +28,7 @@ F32, F64 = 0, 1
 # every symbol the public header declares
 EXPORTED = ["emd_params_default", "emd_plan_create", "emd_plan_destroy", "emd_plan_set_params",
             "emd_plan_set_tiling", "emd_plan_set_gather_tiling", "emd_plan_get_gather_tiling",
-            "emd_plan_autotune", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
+            "emd_plan_autotune", "emd_plan_set_history", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
             "emd_pdhg_solve_replay", "emd_solver_state", "emd_pdhg_solve_resume",
             "emd_adjoint_source", "emd_lsd_misfit", "emd_restrict", "emd_prolong",
             "emd_status_string", "emd_last_error"]
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.emd_plan_set_gather_tiling.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.emd_plan_get_gather_tiling.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.emd_plan_autotune.argtypes = [vp, vp, C.c_int32, vp]
+    lib.emd_plan_set_history.argtypes = [vp, vp, C.c_int32]
     lib.emd_plan_query.argtypes = [vp, C.POINTER(PlanStats)]
     lib.emd_decompose.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.emd_pdhg_solve.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]

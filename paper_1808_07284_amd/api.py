@@ -183,6 +183,20 @@ class Plan:
             os.replace(tmp, path)
         return rows
 
+    def set_history(self, capacity: int):
+        """Record every gather's relative residual at each stop-rule check of later
+        solves in a ring of the last `capacity` checks (0 turns it off).  Returns the
+        float64 [ngather, capacity] device buffer (filled with NaN), or None; read it
+        with residual_history()."""
+        buf = None
+        if capacity > 0:
+            buf = torch.full((self.ngather, int(capacity)), float("nan"), dtype=torch.float64,
+                             device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.load().emd_plan_set_history(self.handle, _ptr(buf), int(capacity) if buf is not None else 0))
+        self._hist = buf  # the library writes into it: keep it alive with the plan
+        return buf
+
     def query(self) -> dict:
         s = L.PlanStats()
         L.check(L.load().emd_plan_query(self.handle, C.byref(s)))
@@ -451,6 +465,24 @@ class Multigrid:
         emd, phi, u, info = emd_pdhg_solve(self.fine, s, phi=phi, u=u, warm_start=True, mass=mass,
                                            emd_out=emd_out, info_out=info_out)
         return emd, phi, u, info, mass
+
+
+def residual_history(plan: Plan, info) -> list:
+    """Per gather, the relative residuals of the last solve's stop-rule checks in
+    iteration order (the ring of Plan.set_history unrolled; at most its capacity,
+    the latest checks).  info: that solve's info records."""
+    hist = getattr(plan, "_hist", None)
+    if hist is None:
+        raise RuntimeError("the plan records no residual history (Plan.set_history)")
+    rec = info_numpy(info) if isinstance(info, torch.Tensor) else info
+    h = hist.cpu().numpy()
+    cap = h.shape[1]
+    out = []
+    for g in range(plan.ngather):
+        n = int(rec["iters"][g]) // plan.params.check_every
+        first = max(n - cap, 0)
+        out.append(np.array([h[g, c % cap] for c in range(first, n)]))
+    return out
 
 
 def info_numpy(info: torch.Tensor) -> np.ndarray:

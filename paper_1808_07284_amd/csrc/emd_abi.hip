@@ -97,6 +97,9 @@ struct emd_plan {
     int graph_chunk = 0;
     std::vector<unsigned char> graph_key;
 
+    double* d_hist = nullptr;  // caller's residual-history ring, or NULL
+    int32_t hist_cap = 0;
+
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int64_t last_sweeps = 0;
     int64_t last_cell_updates = 0;
@@ -301,6 +304,9 @@ SolveScalars scalars(const emd_plan* plan, int ls_mode, const double* replay, in
     sc.replay = replay;
     sc.ld_replay = ld_replay;
     sc.pad = 0;
+    sc.hist = plan->d_hist;
+    sc.hist_cap = plan->hist_cap;
+    sc.pad2 = 0;
     return sc;
 }
 
@@ -770,6 +776,19 @@ emd_status emd_plan_set_gather_tiling(emd_plan* plan, const int32_t* h_rows)
     return build_tiles(plan);
 }
 
+emd_status emd_plan_set_history(emd_plan* plan, double* d_hist, int32_t capacity)
+{
+    g_last_error.clear();
+    if (!plan) return fail(EMD_ERR_NULL_POINTER, "plan is NULL");
+    if (d_hist && capacity < 1) return fail(EMD_ERR_INVALID_ARGUMENT, "capacity must be >= 1");
+    if (!d_hist && capacity != 0) return fail(EMD_ERR_NULL_POINTER, "d_hist is NULL but capacity is not 0");
+    emd_status st = check_device(plan);
+    if (st != EMD_SUCCESS) return st;
+    plan->d_hist = d_hist;
+    plan->hist_cap = d_hist ? capacity : 0;
+    return EMD_SUCCESS;
+}
+
 emd_status emd_plan_get_gather_tiling(const emd_plan* plan, int32_t* h_rows)
 {
     g_last_error.clear();
@@ -795,6 +814,8 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
     if (st != EMD_SUCCESS) return st;
     const emd_params saved = plan->params;
     const std::vector<int> saved_rows = plan->grows;
+    double* const saved_hist = plan->d_hist;
+    plan->d_hist = nullptr;  // the timing solves record no residual history
     plan->params.ls_mode = EMD_LS_FIXED;
     plan->params.max_iter = sweeps - 2;  // max_iter + 2 sweeps: one captured chunk
     plan->params.check_every = sweeps - 2;
@@ -802,6 +823,7 @@ emd_status emd_plan_autotune(emd_plan* plan, const void* s, int32_t sweeps, hipS
     plan->params.sweeps_per_sync = sweeps;
     auto restore = [&](emd_status code) {
         plan->params = saved;
+        plan->d_hist = saved_hist;
         if (code != EMD_SUCCESS) {
             const std::string msg = g_last_error;
             plan->grows = saved_rows;

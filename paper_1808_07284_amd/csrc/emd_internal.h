@@ -97,6 +97,8 @@ struct SolveScalars {
     int32_t max_iter, check_every, max_ls_trials, ls_mode;
     const double* replay;  // LS_REPLAY: [ngather][ld_replay] accepted steps
     int32_t ld_replay, pad;
+    double* hist;          // NULL or [ngather][hist_cap]: residual at every check, a ring
+    int32_t hist_cap, pad2;
 };
 
 // ---------------------------------------------------------------- reductions

@@ -185,6 +185,8 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
         st.transport = gm.cm * l1;
         st.alpha = alpha;
         st.theta = theta;
+        if (sc.hist && writer && lane == 0 && st.iters % sc.check_every == 0)
+            sc.hist[(int64_t)g * sc.hist_cap + (st.iters / sc.check_every - 1) % sc.hist_cap] = st.rel_res;
         if (st.iters % sc.check_every == 0 && st.rel_res <= sc.tol_res) status = ST_CONVERGED;
         else if (st.iters >= sc.max_iter) status = ST_MAX_ITER;
         d.run = 1;

@@ -120,6 +120,7 @@ def test_null_pointers_are_rejected():
     assert lib.emd_decompose(None, None, None, None, None, None, None, None) == 2
     assert lib.emd_pdhg_solve(None, None, None, None, 0, None, None, None, None) == 2
     assert lib.emd_adjoint_source(None, None, None, None, None, None, None, None) == 2
+    assert lib.emd_plan_set_history(None, None, 0) == 2
     assert lib.emd_plan_destroy(None) == 0
     assert lib.emd_status_string(1) == b"EMD_ERR_INVALID_ARGUMENT"
 
