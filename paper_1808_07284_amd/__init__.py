@@ -9,6 +9,6 @@ from ._lib import (EMDError, F32, F64, GATHER_STATUS, LS_FIXED, LS_L1, LS_L2,  #
                    MASS_BALANCE, MASS_NONE, MASS_UNIT)
 from .api import (EMDMisfit, Multigrid, Plan, SolverParams, coarse_descs, emd_adjoint_source,  # noqa: F401
                   emd_decompose, emd_misfit, emd_pdhg_solve, emd_pdhg_solve_replay,
-                  emd_pdhg_solve_resume, info_numpy, lsd_misfit, prolong, residual_history, restrict,
-                  solver_state,
+                  emd_pdhg_solve_resume, info_numpy, lsd_misfit, prolong, residual_history, resolve_failed,
+                  restrict, solver_state,
                   WarmStart)

@@ -485,6 +485,62 @@ def residual_history(plan: Plan, info) -> list:
     return out
 
 
+@dataclass
+class Resolved:
+    """Outcome of resolve_failed: the merged per-gather EMD and solve records, the
+    indices of the gathers solved again, and the FP64 plan of those gathers with its
+    potential and masses (for emd_adjoint_source on them)."""
+    emd: torch.Tensor
+    info: np.ndarray
+    indices: list
+    plan: "Plan | None" = None
+    phi: "torch.Tensor | None" = None
+    mass: "torch.Tensor | None" = None
+
+
+FAILED = ("MAX_ITER", "LS_FAIL", "NONFINITE")
+
+
+def resolve_failed(plan: Plan, pcal, pobs, emd, info, statuses=FAILED,
+                   params: SolverParams | None = None) -> Resolved:
+    """Solve again, in FP64 throughout, the gathers of a solve whose status is one of
+    `statuses` (by name; by default those that stopped without meeting the stop rule).
+    FP32 fields cannot take the residual much below 1e-7, and their rounding can stall
+    the linesearch; the FP64 solve has neither limit.  The gathers are packed into a
+    plan of their own (params: the batch plan's, in FP64, unless given) and solved by
+    the same kernels; their EMD values and records replace those of the batch solve.
+    Gathers with other statuses (converged, zero source, mass imbalance) keep theirs."""
+    rec = (info_numpy(info) if isinstance(info, torch.Tensor) else np.asarray(info)).copy()
+    codes = [L.GATHER_STATUS.index(n) for n in statuses]
+    idx = [g for g in range(plan.ngather) if int(rec["status"][g]) in codes]
+    out = emd.detach().clone()
+    if not idx:
+        return Resolved(out, rec, idx)
+    descs, off = [], 0
+    for g in idx:
+        nr, nt, dx, dt, _ = plan.descs[g]
+        descs.append((nr, nt, dx, dt, off))
+        off += int(nr) * int(nt)
+    prm = dataclasses.replace(params or plan.params, precision=L.F64)
+    sub = Plan(descs, off, prm, device=plan.device)
+
+    def pack(x):
+        plan._check(x, "pcal/pobs")
+        parts = []
+        for g in idx:
+            nr, nt, _, _, o = plan.descs[g]
+            parts.append(x.detach()[int(o):int(o) + int(nr) * int(nt)])
+        return torch.cat(parts).to(torch.float64).contiguous()
+
+    s, mass = emd_decompose(sub, pack(pcal), pack(pobs))
+    e, phi, _, inf = emd_pdhg_solve(sub, s, mass=mass)
+    r = info_numpy(inf)
+    out[idx] = e.to(out.dtype)
+    for k, g in enumerate(idx):
+        rec[g] = r[k]
+    return Resolved(out, rec, idx, sub, phi, mass)
+
+
 def info_numpy(info: torch.Tensor) -> np.ndarray:
     """Per-gather emd_solve_info records as a numpy structured array."""
     return np.frombuffer(info.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
