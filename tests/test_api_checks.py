@@ -1,9 +1,11 @@
-"""Host-side argument checks of the Python binding: every per-gather buffer handed to
-a kernel (masses, EMD values, solve records, step schedules, upstream gradients) must
-be a contiguous tensor of the expected type on the plan's device and large enough,
-or the binding raises before anything reaches the library."""
+"""Host-side logic of the Python binding: every per-gather buffer handed to a kernel
+(masses, EMD values, solve records, step schedules, upstream gradients) must be a
+contiguous tensor of the expected type on the plan's device and large enough, or the
+binding raises before anything reaches the library; and the residual-history ring is
+unrolled into check order."""
 from types import SimpleNamespace
 
+import numpy as np
 import pytest
 import torch
 
@@ -49,3 +51,22 @@ def test_upstream_gradients_are_one_per_gather():
     assert g.dtype == torch.float64 and g.tolist() == [1.0, 2.0, 3.0]
     with pytest.raises(ValueError, match="gbar"):
         A._gbar(plan, torch.ones(2))
+
+
+def test_residual_history_unrolls_the_ring():
+    # checks c = 1..n land in slot (c - 1) % capacity; the unrolled history lists the
+    # last min(n, capacity) checks in iteration order
+    cap, ce = 4, 10
+    rec = np.zeros(3, dtype=A.INFO_DTYPE)
+    rec["iters"] = [70, 30, 0]  # 7 checks (wrapped), 3 checks, none
+    ring = np.full((3, cap), np.nan)
+    for g, n in enumerate((7, 3, 0)):
+        for c in range(1, n + 1):
+            ring[g, (c - 1) % cap] = 100 * g + c
+    plan = SimpleNamespace(ngather=3, params=SimpleNamespace(check_every=ce), _hist=torch.from_numpy(ring))
+    h = A.residual_history(plan, rec)
+    assert h[0].tolist() == [4, 5, 6, 7]
+    assert h[1].tolist() == [101, 102, 103]
+    assert h[2].size == 0
+    with pytest.raises(RuntimeError):
+        A.residual_history(SimpleNamespace(ngather=1, params=plan.params, _hist=None), rec[:1])
