@@ -7,6 +7,10 @@ benchmark's ``cpu_baseline`` leg may import this package; the library in
 The arithmetic lives in ``emd_oracle.c`` (plain loops, double precision).  This
 module only marshals numpy arrays into it with ctypes and builds it with gcc on
 first use when the shared object is missing.
+
+Parity unpinned: the 2D potential phi and the path of iterates and steps (no closed
+form; checked only as parity of the same algorithm).  The EMD, the transport, the
+operators, the adjoint and the grid transfers are pinned by the tests.
 """
 from __future__ import annotations
 

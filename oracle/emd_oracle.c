@@ -36,6 +36,14 @@
  * l1 norms as an option; u and phi start at 0 unless warm-started; a gather of
  * one receiver (or one sample) drops that axis' terms and uses a unit spacing
  * for it in the cell measure.
+ *
+ * Pins (the tests): the EMD and transport against the 1D closed form, exact
+ * transport LPs on small grids and a duality bracket; the operators against the
+ * adjoint identity, the Gershgorin bound and brute-force prox and dual steps; the
+ * adjoint against finite differences; the grid transfers against conservation and
+ * linear reproduction.  Parity unpinned: the 2D potential phi itself (not unique
+ * where no mass moves) and the sequence of iterates and steps of Algorithm 1 have
+ * no closed form; they are checked only as parity of the same algorithm.
  */
 #include <math.h>
 #include <stdint.h>
