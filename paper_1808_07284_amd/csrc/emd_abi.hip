@@ -519,7 +519,7 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     const int64_t max_sweeps = round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
     int64_t sweeps = 0;
     // Finished gathers leave the sweep's tile tables: once the running gathers hold at
-    // most 7/8 of the tables' cells, the chains are rebuilt from them alone and spread
+    // most 15/16 of the tables' cells, the chains are rebuilt from them alone and spread
     // over the XCDs again.  Tiles keep their shape and partial-sum slots, so every
     // decision, and hence every result, is bitwise the same as with the full table.
     int64_t table_cells = plan->cells;
@@ -550,7 +550,7 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
                 else ++out;
             }
             known_out = out;
-            if (live > 0 && live * 8 <= table_cells * 7) {
+            if (live > 0 && live * 16 <= table_cells * 15) {
                 cst = build_chains<T>(plan, sel, sa, ch, stream);
                 if (cst != EMD_SUCCESS) return cst;
                 table_cells = live;
