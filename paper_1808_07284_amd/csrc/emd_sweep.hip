@@ -59,12 +59,63 @@ __device__ __forceinline__ double first_candidate(double ak, double tk, double a
     return alpha;
 }
 
+// The fixed order in which a gather's decision sums its tiles' records, so that
+// every wave forming it, under any tiling and any narrowing of the table, gets the
+// same bits: record p goes to quarter (p / 64) % 4 and lane p % 64; each lane adds
+// its records of a quarter in slot order, the quarter's lanes are added by
+// wave_sum, and the quarters are added in order ((S0 + S1) + S2) + S3.
+template <int NP>
+__device__ __forceinline__ void quarter_sum(const double* __restrict__ src, int n, int w,
+                                            double (&s)[NP])
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    for (int p = w * WAVE + lane; p < n; p += 4 * WAVE) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc[q] += src[(int64_t)p * NP + q];
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) s[q] = wave_sum(acc[q]);
+}
+
+// red != NULL: the four waves of this block each sum one quarter (wave w, quarter w)
+// and exchange them through red (LDS, 4 * NP doubles) at one block barrier that
+// every wave of the block reaches; otherwise this wave sums all four quarters.
+template <int NP>
+__device__ __forceinline__ void decision_sums(const double* __restrict__ src, int n, int w,
+                                              double* red, double (&out)[NP])
+{
+    if (red) {
+        double s[NP];
+        quarter_sum<NP>(src, n, w, s);
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q) red[w * NP + q] = s[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NP; ++q) out[q] = ((red[q] + red[NP + q]) + red[2 * NP + q]) + red[3 * NP + q];
+    } else {
+        double s[NP];
+        quarter_sum<NP>(src, n, 0, out);
+        for (int k = 1; k < 4; ++k) {
+            quarter_sum<NP>(src, n, k, s);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) out[q] += s[q];
+        }
+    }
+}
+
 // Runs on every lane of a wave; returns the same decision on every lane.
 // ABS: the l1 form of the linesearch test (records of NPART_L1 doubles).
-// pb: buffer parity of the gather's fields in this sweep.
+// pb: buffer parity of the gather's fields in this sweep.  w, red: this wave's index
+// in its block and the block's exchange buffer for the record sums (see
+// decision_sums; NULL when the wave sums alone).
 template <typename T, bool ABS>
 __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta& gm,
-                           bool writer, int pb)
+                           bool writer, int pb, int w, double* red)
 {
     const GState* __restrict__ sin = a.gst[p] + g;
     GState* __restrict__ sout = a.gst[p ^ 1] + g;
@@ -98,7 +149,7 @@ __device__ Decision decide(const SweepArgs<T>& a, int p, int g, const GatherMeta
     }
     constexpr int NP = ABS ? NPART_L1 : NPART;
     double q[NP];
-    reduce_records(a.part[p] + (int64_t)gm.tile_base * NP, gm.ntiles, q);
+    decision_sums<NP>(a.part[p] + (int64_t)gm.tile_base * NP, gm.ntiles, w, red, q);
     const double aa = q[0];
     const double l1 = ABS ? q[1] : q[6], l2 = ABS ? q[2] : q[7];
     const double ak = st.alpha, tk = st.theta;
@@ -875,7 +926,8 @@ __device__ void eval_tile(const TileCtx<T>& c, double (&acc)[NPART_L1])
 // gather (dual step only) always marches down.  ABS: l1 linesearch test.
 // p: sweep parity (partials, scalar state); pb: buffer parity of the fields.
 template <typename T, bool EDGE, bool UP, bool ABS>
-__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb)
+__device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb,
+                           int w, double* red)
 {
     constexpr int V = Vec<T>::N;
     constexpr int NP = ABS ? NPART_L1 : NPART;
@@ -921,7 +973,7 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const Tile& tl, const GatherMe
     using Pipeline = typename std::conditional<UP, PipeUp<T, EDGE, ABS>, Pipe<T, EDGE, ABS>>::type;
     Pipeline P(c);
     P.start();
-    const Decision d = decide<T, ABS>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb);
+    const Decision d = decide<T, ABS>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
     if (!d.run) return;
     P.c.beta = T(d.beta);
     P.c.theta = T(d.theta);
@@ -973,11 +1025,43 @@ template <typename T, bool ABS>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
 {
     constexpr int V = Vec<T>::N;
-    const int tid = uniform(xcd_logical_block() * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    constexpr int NP = ABS ? NPART_L1 : NPART;
+    constexpr int WPB = 256 / WAVE;  // waves per block (4: the quarters of the record sums)
+    static_assert(WPB == 4, "the decision sums are split in four quarters");
+    __shared__ double red[WPB * NP];
+    const int w = uniform((int)threadIdx.x / WAVE);
+    const int first = uniform(xcd_logical_block() * WPB);  // table entry of wave 0
+    const int tid = first + w;
     if (tid >= a.ntiles) return;
+    // When every real entry of this block belongs to one running gather past its
+    // first sweep, its four waves (padding entries included) share the work of that
+    // gather's decision sums; every wave of such a block reaches the one barrier in
+    // decision_sums.  Each wave works this out from the same four entries.
+    int gb = -1;
+    bool split = first + WPB <= a.ntiles;
+    for (int k = 0; k < WPB && split; ++k) {
+        const int gk = uniform(a.tiles[first + k].g);
+        if (gk < 0) continue;
+        if (gb < 0) gb = gk;
+        else if (gk != gb) split = false;
+    }
+    if (gb < 0) split = false;
+    if (split) {
+        const GState* sb = a.gst[parity] + gb;
+        split = uniform(sb->status) == ST_RUNNING && uniform(sb->started) != 0;
+    }
     const Tile tl = a.tiles[tid];
     const int g = uniform(tl.g);
-    if (g < 0) return;  // padding entry
+    if (g < 0) {
+        // padding entry: only its quarter of the block gather's decision sums
+        if (split) {
+            const GatherMeta mb = a.meta[gb];
+            double s[NP];
+            decision_sums<NP>(a.part[parity] + (int64_t)mb.tile_base * NP, mb.ntiles, w, red, s);
+        }
+        return;
+    }
+    double* const xred = split ? red : nullptr;
     const GatherMeta gm = a.meta[g];
     const GState* gs = a.gst[parity] + g;
     if (gs->status != ST_RUNNING) {
@@ -993,11 +1077,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     // odd strips march up
     const bool up = ((tl.r0 / gm.rows) & 1) != 0;
     if (edge) {
-        if (up) sweep_tile<T, true, true, ABS>(a, tl, gm, parity, pb);
-        else sweep_tile<T, true, false, ABS>(a, tl, gm, parity, pb);
+        if (up) sweep_tile<T, true, true, ABS>(a, tl, gm, parity, pb, w, xred);
+        else sweep_tile<T, true, false, ABS>(a, tl, gm, parity, pb, w, xred);
     } else {
-        if (up) sweep_tile<T, false, true, ABS>(a, tl, gm, parity, pb);
-        else sweep_tile<T, false, false, ABS>(a, tl, gm, parity, pb);
+        if (up) sweep_tile<T, false, true, ABS>(a, tl, gm, parity, pb, w, xred);
+        else sweep_tile<T, false, false, ABS>(a, tl, gm, parity, pb, w, xred);
     }
 }
 
