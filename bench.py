@@ -343,7 +343,7 @@ def main():
                       "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
                       "linesearch": args.ls,
                       "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
-                      "tile_rows": heights if heights else (args.rows or 16),
+                      "tile_rows": heights if heights else (args.rows or plan.query()["rows_per_tile"]),
                       "tile_rows_per_gather": plan.gather_tiling()},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
