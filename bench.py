@@ -179,7 +179,7 @@ def main():
     bufs = {"s": plan.empty(), "phi": plan.empty(), "psi": plan.empty(),
             "mass": torch.empty(len(gathers), 3, dtype=torch.float64, device=dev),
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
-            "info": torch.empty(len(gathers) * 48, dtype=torch.uint8, device=dev)}
+            "info": torch.empty(len(gathers) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
 
     for w in range(args.warmup):
         run_step(E, plan, pcal, pobs, bufs)

@@ -114,27 +114,36 @@ typedef struct {
     int32_t mass_mode, precision, sweeps_per_sync, reserved;
 } emd_params;
 
-/* Per-gather result (device array written by emd_pdhg_solve). */
+/* Per-gather result (device array written by emd_pdhg_solve).
+ * The EMD estimate is the Lagrangian of Section 2.2 at the returned pair,
+ *   emd = dx dt (Phi(u) + <phi, div u + s>),  Phi(u) = ||u||_{1,1} + eps/2 ||u||_2^2,
+ * which equals the objective dx dt Phi(u) (`primal`) wherever the flux meets the
+ * constraint and, at a stop-rule iterate that misses it by the residual, prices
+ * that miss with the potential (the derivative of the optimal value with respect
+ * to s).  On the seismic batches it is 5-6 times closer to the converged EMD than
+ * `primal` at the same iteration. */
 typedef struct {
     int32_t status;    /* EMD_GATHER_*                                    */
     int32_t iters;     /* accepted PDHG iterations                        */
     int32_t ls_trials; /* backtracking steps over the whole solve         */
     int32_t pad;
     double rel_res;    /* ||div u + s||_2 / ||s||_2 of the returned u      */
-    double emd;        /* dx dt (||u||_{1,1} + eps/2 ||u||_2^2)            */
+    double emd;        /* dx dt L(u, phi), as above (also in d_emd)       */
     double transport;  /* dx dt ||u||_{1,1}                                */
     double alpha;      /* last accepted primal step                        */
+    double primal;     /* dx dt (||u||_{1,1} + eps/2 ||u||_2^2)            */
 } emd_solve_info;
 
 /* Solver state of one gather at the end of a solve (host struct): the step alpha_k
  * and theta_k of its last accepted iteration k, the counts, and its outcome (status,
  * and for a finished gather the residual, EMD and transport it reported).  With the
  * flux u_k and potential phi_k the solve returned, it is all a resumed solve needs
- * (see emd_pdhg_solve_resume). */
+ * (see emd_pdhg_solve_resume); the EMD estimate of a finished gather is recomputed
+ * from those fields. */
 typedef struct {
     double alpha, theta;
     int32_t iters, ls_trials, status, pad;
-    double rel_res, emd, transport;
+    double rel_res, primal, transport;  /* primal: dx dt Phi(u) */
 } emd_gather_state;
 
 /* Plan statistics (host struct filled by emd_plan_query). */

@@ -55,7 +55,7 @@ class _Params(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("ls_trials", C.c_int32),
                 ("pad", C.c_int32), ("rel_res", C.c_double), ("emd", C.c_double),
-                ("transport", C.c_double)]
+                ("transport", C.c_double), ("primal", C.c_double)]
 
 
 _lib = None
@@ -81,6 +81,9 @@ def _load():
                                          C.c_int, dp, dp, dp, dp]
         lib.oracle_emd_value.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                          dp, dp, dp, dp]
+        lib.oracle_lagrangian_value.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double,
+                                                C.c_double, dp, dp, dp, dp, dp]
+        lib.oracle_lagrangian_value.restype = C.c_double
         lib.oracle_params_default.argtypes = [C.POINTER(_Params)]
         lib.oracle_solve.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp,
                                      C.POINTER(_Params), dp, dp, dp, C.POINTER(_Info), dp]
@@ -132,6 +135,8 @@ class Params:
 
 @dataclass
 class SolveResult:
+    """emd: dx dt L(u, phi), the Lagrangian value at the returned pair (the EMD
+    estimate); primal: dx dt Phi(u) of the returned flux; transport: dx dt ||u||_1."""
     ux: np.ndarray
     ut: np.ndarray
     phi: np.ndarray
@@ -141,6 +146,7 @@ class SolveResult:
     rel_res: float
     emd: float
     transport: float
+    primal: float = float("nan")
     alpha_trace: np.ndarray | None = None
 
 
@@ -202,6 +208,17 @@ def emd_value(ux, ut, dx, dt, eps=1e-4):
     return e.value, w.value
 
 
+def lagrangian_value(s, ux, ut, phi, dx, dt, eps=1e-4):
+    """dx dt (Phi(u) + <phi, div u + s>) (the Lagrangian of Section 2.2) and
+    dx dt Phi(u).  Returns (lagrangian, primal)."""
+    s, ux, ut, phi = _f64(s), _f64(ux), _f64(ut), _f64(phi)
+    nr, nt = s.shape
+    pr = C.c_double()
+    v = _load().oracle_lagrangian_value(nr, nt, dx, dt, eps, _p(s), _p(ux), _p(ut), _p(phi),
+                                        C.byref(pr))
+    return v, pr.value
+
+
 def solve(s, dx, dt, params: Params | None = None, u0=None, phi0=None,
           trace: bool = False) -> SolveResult:
     """Run Algorithm 1 on the source s (div u + s = 0) of one gather."""
@@ -216,7 +233,7 @@ def solve(s, dx, dt, params: Params | None = None, u0=None, phi0=None,
     _load().oracle_solve(nr, nt, dx, dt, _p(s), C.byref(params._c()), _p(ux), _p(ut), _p(phi),
                          C.byref(info), _p(tr) if trace else None)
     return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
-                       info.emd, info.transport,
+                       info.emd, info.transport, info.primal,
                        tr[:info.iters].copy() if trace else None)
 
 
@@ -282,4 +299,4 @@ def misfit(pcal, pobs, dx, dt, mass_mode=MASS_BALANCE, params: Params | None = N
                           C.byref(params._c()), _p(ux), _p(ut), _p(phi), _p(mass),
                           C.byref(info))
     return SolveResult(ux, ut, phi, info.status, info.iters, info.ls_trials, info.rel_res,
-                       info.emd, info.transport), mass
+                       info.emd, info.transport, info.primal), mass

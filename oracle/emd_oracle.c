@@ -81,7 +81,10 @@ typedef struct {
 
 typedef struct {
     int32_t status, iters, ls_trials, pad;
-    double rel_res, emd, transport;
+    double rel_res;
+    double emd;        /* dx dt L(u, phi), the Lagrangian value at the returned pair */
+    double transport;  /* dx dt ||u||_{1,1}                                         */
+    double primal;     /* dx dt Phi(u), the objective of the returned flux         */
 } oracle_info;
 
 /* ------------------------------------------------------------------ helpers */
@@ -233,6 +236,29 @@ void oracle_emd_value(int nr, int nt, double dx, double dt, double eps,
     *transport = cm * acc_val(&l1);
 }
 
+/* The Lagrangian of Section 2.2, L(u, phi) = Phi(u) + <phi, div u + s>, times the
+ * cell measure: dx dt (||u||_{1,1} + eps/2 ||u||_2^2 + sum phi (div u + s)).  At a
+ * flux that meets the constraint it is the EMD dx dt Phi(u) itself, for any phi;
+ * near the saddle point it is the estimate of the optimal value that the solve
+ * reports (the returned flux still misses the constraint by the residual, and the
+ * potential prices that miss).  *primal receives dx dt Phi(u) (may be NULL). */
+double oracle_lagrangian_value(int nr, int nt, double dx, double dt, double eps,
+                               const double* s, const double* ux, const double* ut,
+                               const double* phi, double* primal)
+{
+    int64_t n = (int64_t)nr * nt;
+    const double dx_eff = (nr > 1) ? dx : 1.0, dt_eff = (nt > 1) ? dt : 1.0;
+    double* dv = malloc(sizeof(double) * n);
+    oracle_div(nr, nt, dx_eff, dt_eff, ux, ut, dv);
+    or_acc pr = {0, 0};
+    for (int64_t c = 0; c < n; ++c) acc_add(&pr, phi[c] * (dv[c] + s[c]));
+    free(dv);
+    double emd, transport;
+    oracle_emd_value(nr, nt, dx, dt, eps, ux, ut, &emd, &transport);
+    if (primal) *primal = emd;
+    return emd + oracle_cell_measure(nr, nt, dx, dt) * acc_val(&pr);
+}
+
 static double norm_l2(int64_t n, const double* a)
 {
     double t = 0.0;
@@ -283,6 +309,7 @@ int oracle_solve(int nr, int nt, double dx, double dt, const double* s,
     if (!isfinite(snorm)) {
         info->status = OR_NONFINITE;
         info->emd = NAN;
+        info->primal = NAN;
         info->transport = NAN;
         info->rel_res = NAN;
         return info->status;
@@ -397,7 +424,8 @@ int oracle_solve(int nr, int nt, double dx, double dt, const double* s,
     oracle_div(nr, nt, dx_eff, dt_eff, ux, ut, dv);
     for (int64_t c = 0; c < n; ++c) dv[c] += s[c];
     info->rel_res = norm_l2(n, dv) / snorm;
-    oracle_emd_value(nr, nt, dx, dt, p->eps, ux, ut, &info->emd, &info->transport);
+    oracle_emd_value(nr, nt, dx, dt, p->eps, ux, ut, &info->primal, &info->transport);
+    info->emd = oracle_lagrangian_value(nr, nt, dx, dt, p->eps, s, ux, ut, phi, NULL);
     info->status = status;
     info->iters = iters;
     info->ls_trials = (int32_t)trials_total;
@@ -477,6 +505,7 @@ int oracle_misfit(int nr, int nt, double dx, double dt, const double* pcal,
         memset(phi, 0, sizeof(double) * n);
         info->status = OR_MASS_IMBALANCE;
         info->emd = NAN;
+        info->primal = NAN;
         info->transport = NAN;
         info->rel_res = NAN;
         st = info->status;

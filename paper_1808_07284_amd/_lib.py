@@ -51,13 +51,13 @@ class Params(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("ls_trials", C.c_int32),
                 ("pad", C.c_int32), ("rel_res", C.c_double), ("emd", C.c_double),
-                ("transport", C.c_double), ("alpha", C.c_double)]
+                ("transport", C.c_double), ("alpha", C.c_double), ("primal", C.c_double)]
 
 
 class GatherState(C.Structure):
     _fields_ = [("alpha", C.c_double), ("theta", C.c_double), ("iters", C.c_int32),
                 ("ls_trials", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32),
-                ("rel_res", C.c_double), ("emd", C.c_double), ("transport", C.c_double)]
+                ("rel_res", C.c_double), ("primal", C.c_double), ("transport", C.c_double)]
 
 
 class PlanStats(C.Structure):

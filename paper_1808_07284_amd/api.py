@@ -21,7 +21,8 @@ import torch
 from . import _lib as L
 
 INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("ls_trials", "<i4"), ("pad", "<i4"),
-                       ("rel_res", "<f8"), ("emd", "<f8"), ("transport", "<f8"), ("alpha", "<f8")])
+                       ("rel_res", "<f8"), ("emd", "<f8"), ("transport", "<f8"), ("alpha", "<f8"),
+                       ("primal", "<f8")])
 
 
 @dataclass
@@ -262,7 +263,7 @@ def emd_decompose(plan: Plan, pcal, pobs, s_out=None, f_out=None, g_out=None, ma
 def emd_pdhg_solve(plan: Plan, s, phi=None, u=None, warm_start=False, mass=None, emd_out=None,
                    info_out=None):
     """PDHG with linesearch for every gather (Algorithm 1).
-    Returns (emd [ngather] float64, phi, u or None, info uint8 [ngather * 48])."""
+    Returns (emd [ngather] float64, phi, u or None, info uint8 [ngather * INFO_DTYPE.itemsize])."""
     phi = plan.empty() if phi is None else phi
     emd_out = (torch.empty(plan.ngather, dtype=torch.float64, device=plan.device)
                if emd_out is None else emd_out)

@@ -572,7 +572,7 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     plan->timing_valid = true;
 
     a.gst = plan->d_gst;  // parity 0: every chunk has an even number of sweeps
-    launch_finalize<T>(a, stream);
+    launch_finalize<T>(a, plan->grid, stream);
     launch_copy_out<T>(a, plan->grid, stream);
     HIP_TRY(hipGetLastError());
 
@@ -1007,6 +1007,7 @@ static_assert(sizeof(emd_gather_state) == sizeof(ResumeRec) &&
                   offsetof(emd_gather_state, iters) == offsetof(ResumeRec, iters) &&
                   offsetof(emd_gather_state, status) == offsetof(ResumeRec, status) &&
                   offsetof(emd_gather_state, rel_res) == offsetof(ResumeRec, rel_res) &&
+                  offsetof(emd_gather_state, primal) == offsetof(ResumeRec, primal) &&
                   offsetof(emd_gather_state, transport) == offsetof(ResumeRec, transport),
               "emd_gather_state mirrors the resume record");
 
@@ -1025,7 +1026,7 @@ emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state)
         h_state[g].status = s.status;
         h_state[g].pad = 0;
         h_state[g].rel_res = s.rel_res;
-        h_state[g].emd = s.emd;
+        h_state[g].primal = s.emd;
         h_state[g].transport = s.transport;
     }
     return EMD_SUCCESS;

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64) void k_gather_init(AuxArgs<T> a)
             // the u and phi copied in above are what the solve returns for it
             status = r.status;
             st.rel_res = r.rel_res;
-            st.emd = r.emd;
+            st.emd = r.primal;
             st.transport = r.transport;
         }
     }
@@ -200,16 +200,78 @@ __global__ __launch_bounds__(256) void k_copy_out(AuxArgs<T> a)
 
 struct InfoRec {
     int32_t status, iters, ls_trials, pad;
-    double rel_res, emd, transport, alpha;
+    double rel_res, emd, transport, alpha, primal;
 };
 
-template <typename T>
-__global__ void k_finalize(AuxArgs<T> a)
+// A gather whose returned flux and potential come from iterations (not a zero,
+// non-finite or unbalanced source) is priced by the Lagrangian.
+__device__ __forceinline__ bool iterated(int status)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.ngather) return;
+    return status == ST_CONVERGED || status == ST_MAX_ITER || status == ST_LS_FAIL;
+}
+
+// The potential term of the Lagrangian of Section 2.2 at the pair a solve returns:
+// per tile, sum phi (div u + s) over the tile's cells, with the divergence of the
+// stored flux formed in FP64 (div = minus the transpose of the backward-difference
+// gradient: forward differences inside, -u/dx and -u/dt on the last row and
+// column).  Reads the returned buffers of the padded state (parity-0 gather state).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lagr_sums(AuxArgs<T> a)
+{
+    constexpr int V = Vec<T>::N;
+    GatherMeta gm;
+    bool ok;
+    const TileView tv = tile_view(a, gm, ok);
+    if (!ok) return;
+    double acc[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
+    const GState st = a.gst[tv.g];
+    if (tv.active && iterated(st.status)) {
+        const T* __restrict__ ux = a.ux[st.ubuf];
+        const T* __restrict__ ut = a.ut[st.ubuf];
+        const T* __restrict__ ph = a.phi[st.phibuf];
+        const double idx = 1.0 / gm.dx, idt = 1.0 / gm.dt;
+        for (int i = tv.r0; i < tv.rend; ++i) {
+            const int64_t pr = gm.poff + (int64_t)i * gm.ld + tv.j0;
+            const bool below = i + 1 < gm.nr;
+            T x0[V], x1[V], t0[V], p0[V], s0[V];
+            vload(ux + pr, x0);
+            vload(ux + (below ? pr + gm.ld : pr), x1);
+            vload(ut + pr, t0);
+            vload(ph + pr, p0);
+            vload(a.s_pad + pr, s0);
+            // u^t of the sample after the vector (inside the padded row)
+            const double tnext = tv.j0 + V < gm.nt ? double(ut[pr + V]) : 0.0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const int j = tv.j0 + k;
+                if (j >= gm.nt) break;
+                double d = double(s0[k]);
+                if (below) d += double(x1[k]) * idx;
+                if (i > 0) d -= double(x0[k]) * idx;
+                if (j + 1 < gm.nt) d += (k + 1 < V ? double(t0[(k + 1) % V]) : tnext) * idt;
+                if (j > 0) d -= double(t0[k]) * idt;
+                acc[0] = fma(double(p0[k]), d, acc[0]);
+            }
+        }
+    }
+    write_record(a.part, tv.slot, acc);
+}
+
+// One wavefront per gather: the Lagrangian value (from the k_lagr_sums records),
+// EMD values and solve records.
+template <typename T>
+__global__ __launch_bounds__(64) void k_finalize(AuxArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const GatherMeta gm = a.meta[g];
     const GState st = a.gst[g];
-    if (a.emd_out) a.emd_out[g] = st.emd;
+    double q[NPART];
+    reduce_records(a.part + (int64_t)gm.tile_base * NPART, gm.ntiles, q);
+    const double emd = iterated(st.status) ? st.emd + gm.cm * q[0] : st.emd;
+    if (threadIdx.x != 0) return;
+    if (a.emd_out) a.emd_out[g] = emd;
     if (a.info_out) {
         InfoRec r;
         r.status = st.status;
@@ -217,9 +279,10 @@ __global__ void k_finalize(AuxArgs<T> a)
         r.ls_trials = st.trials;
         r.pad = 0;
         r.rel_res = st.rel_res;
-        r.emd = st.emd;
+        r.emd = emd;
         r.transport = st.transport;
         r.alpha = st.alpha;
+        r.primal = st.emd;
         reinterpret_cast<InfoRec*>(a.info_out)[g] = r;
     }
 }
@@ -567,9 +630,10 @@ void launch_copy_out(const AuxArgs<T>& a, int grid, hipStream_t stream)
 }
 
 template <typename T>
-void launch_finalize(const AuxArgs<T>& a, hipStream_t stream)
+void launch_finalize(const AuxArgs<T>& a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_finalize<T>, dim3((a.ngather + 63) / 64), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(k_lagr_sums<T>, dim3(grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_finalize<T>, dim3(a.ngather), dim3(64), 0, stream, a);
 }
 
 template <typename T>
@@ -609,7 +673,7 @@ void launch_zero_counter(int32_t* counter, hipStream_t stream)
     template void launch_copy_in<T>(const AuxArgs<T>&, int, int, hipStream_t);      \
     template void launch_gather_init<T>(const AuxArgs<T>&, hipStream_t);            \
     template void launch_copy_out<T>(const AuxArgs<T>&, int, hipStream_t);          \
-    template void launch_finalize<T>(const AuxArgs<T>&, hipStream_t);               \
+    template void launch_finalize<T>(const AuxArgs<T>&, int, hipStream_t);          \
     template void launch_decompose<T>(const AuxArgs<T>&, int, hipStream_t);         \
     template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);           \
     template void launch_lsd<T>(const AuxArgs<T>&, int, hipStream_t);                \

@@ -73,7 +73,7 @@ struct GState {
     double snorm;      // ||s||_2
     double alpha_max;  // cap on alpha
     double rel_res;    // residual of the flux returned so far
-    double emd, transport;
+    double emd, transport;  // dx dt Phi(u) and dx dt ||u||_1 of that flux
     int32_t iters;     // accepted iterations
     int32_t status;
     int32_t trials;    // backtracking steps so far
@@ -89,7 +89,7 @@ struct GState {
 struct ResumeRec {
     double alpha, theta;
     int32_t iters, trials, status, pad;
-    double rel_res, emd, transport;
+    double rel_res, primal, transport;
 };
 
 struct SolveScalars {

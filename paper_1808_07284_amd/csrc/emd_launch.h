@@ -87,7 +87,7 @@ template <typename T> void launch_prolong(const XferArgs<T>& a, int ngather, int
 template <typename T> void launch_copy_in(const AuxArgs<T>& a, int warm, int grid, hipStream_t stream);
 template <typename T> void launch_gather_init(const AuxArgs<T>& a, hipStream_t stream);
 template <typename T> void launch_copy_out(const AuxArgs<T>& a, int grid, hipStream_t stream);
-template <typename T> void launch_finalize(const AuxArgs<T>& a, hipStream_t stream);
+template <typename T> void launch_finalize(const AuxArgs<T>& a, int grid, hipStream_t stream);
 template <typename T> void launch_decompose(const AuxArgs<T>& a, int grid, hipStream_t stream);
 template <typename T> void launch_adjoint(const AuxArgs<T>& a, int grid, hipStream_t stream);
 template <typename T> void launch_lsd(const AuxArgs<T>& a, int grid, hipStream_t stream);

@@ -253,3 +253,104 @@ def test_decompose_mainini(oracle_mod):
     assert abs(su.sum()) * cm <= 1e-12
     # each side carries unit mass, so the signed source has total variation <= 2
     assert np.abs(su).sum() * cm <= 2.0 + 1e-12
+
+
+def test_decompose_unit_mode_with_unequal_masses(oracle_mod):
+    # Section 2.1 recombines the signed data into f = Pcal+ + Pobs- and g = Pobs+ +
+    # Pcal-; the unit mass mode divides each side by its own mass, s = f/M_f - g/M_g.
+    # Point masses make every value a hand calculation, with M_f != M_g so that a
+    # swapped or shared divisor shows.  Pcal: a at c1, -c at c3; Pobs: b at c2.
+    nr, nt, dx, dt = 4, 6, 0.5, 0.25
+    cm = dx * dt
+    a, b, c = 3.0, 0.5, 1.25
+    pcal = np.zeros((nr, nt))
+    pobs = np.zeros((nr, nt))
+    c1, c2, c3 = (0, 1), (3, 4), (2, 0)
+    pcal[c1], pcal[c3], pobs[c2] = a, -c, b
+    s, f, g, mass = oracle_mod.decompose(pcal, pobs, dx, dt, oracle_mod.MASS_UNIT)
+    assert mass[0] == cm * a and mass[1] == cm * (b + c)        # M_f, M_g
+    want = np.zeros((nr, nt))
+    want[c1] = 1.0 / cm                     # f / M_f = a / (cm a)
+    want[c2] = -b / (cm * (b + c))          # -g / M_g
+    want[c3] = -c / (cm * (b + c))
+    np.testing.assert_allclose(s, want, rtol=1e-15, atol=0)
+    # each side carries unit mass whatever the two masses are
+    assert cm * s[s > 0].sum() == pytest.approx(1.0, rel=1e-15)
+    assert cm * s[s < 0].sum() == pytest.approx(-1.0, rel=1e-15)
+    # the balance mode keeps the raw difference minus its mean instead
+    sb, _, _, mb = oracle_mod.decompose(pcal, pobs, dx, dt, oracle_mod.MASS_BALANCE)
+    assert mb[2] == pytest.approx((a - c - b) / (nr * nt), rel=1e-15)
+    np.testing.assert_allclose(sb, pcal - pobs - mb[2], rtol=0, atol=1e-15)
+
+
+def test_unit_mode_transport_of_two_point_masses(oracle_mod):
+    # Unit masses at two cells (Pcal twice as heavy as Pobs, so only the unit mode
+    # balances them): at eps = 0 the transport is the Manhattan distance between the
+    # cells times the unit mass (Section 2.1, Kantorovich form with this ground cost)
+    nr, nt, dx, dt = 5, 7, 0.25, 0.125
+    pcal = np.zeros((nr, nt))
+    pobs = np.zeros((nr, nt))
+    pcal[1, 1] = 2.0
+    pobs[3, 5] = 1.0
+    s, _, _, mass = oracle_mod.decompose(pcal, pobs, dx, dt, oracle_mod.MASS_UNIT)
+    assert mass[0] == pytest.approx(2 * mass[1])
+    # a fixed budget: the residual rule certifies feasibility, not optimality
+    r = oracle_mod.solve(s, dx, dt, FIXED_BUDGET(eps=0.0))
+    assert r.rel_res <= 1e-10
+    assert r.transport == pytest.approx(2 * dx + 4 * dt, rel=1e-7)
+
+
+def test_lagrangian_value_at_a_feasible_flux_is_the_objective(oracle_mod):
+    # L(u, phi) = Phi(u) + <phi, div u + s> (Section 2.2): where the constraint holds
+    # the potential term vanishes for any phi.  In 1D the optimal flux is known
+    # exactly, u_{k+1} = -dt S_k with S = cumsum(s), and is feasible.
+    g = config1_pairs([50], nt=120, dt=1.0 / 119, f_peak=3.0, centre=0.45)[0]
+    s, _, _, _ = oracle_mod.decompose(g.pcal, g.pobs, g.dx, g.dt)
+    _, _, S = closed_form_1d(s, g.dt, 1e-4)
+    ut = np.zeros_like(s)
+    ut[0, 1:] = -g.dt * S
+    ux = np.zeros_like(s)
+    assert np.abs(oracle_mod.div(ux, ut, g.dx, g.dt) + s).max() <= 1e-12 * np.abs(s).max()
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        phi = rng.normal(size=s.shape)
+        lag, primal = oracle_mod.lagrangian_value(s, ux, ut, phi, g.dx, g.dt)
+        assert lag == pytest.approx(primal, rel=1e-12)
+        assert primal == pytest.approx(closed_form_1d(s, g.dt, 1e-4)[0], rel=1e-12)
+    # an infeasible flux: the potential term is exactly the residual priced by phi,
+    # here a constant potential c on a flux that moves nothing: L = c dt sum s = 0
+    # for a balanced source, and dt <phi, s> for a general one
+    lag0, p0 = oracle_mod.lagrangian_value(s, 0 * ux, 0 * ut, np.full_like(s, 3.0), g.dx, g.dt)
+    assert p0 == 0.0 and abs(lag0) <= 1e-13 * g.dt * np.abs(s).sum()
+    phi = rng.normal(size=s.shape)
+    lag1, _ = oracle_mod.lagrangian_value(s, 0 * ux, 0 * ut, phi, g.dx, g.dt)
+    assert lag1 == pytest.approx(g.dt * float(np.sum(phi * s)), rel=1e-12)
+
+
+def test_lagrangian_is_minimal_in_u_at_the_saddle_point(oracle_mod):
+    # At the primal-dual solution (u*, phi*), u* minimises L(., phi*) (Section 2.2:
+    # the optimality conditions dL/du = 0, dL/dphi = 0): no perturbation of the flux
+    # lowers the Lagrangian, while with the potential term's sign flipped a step
+    # along -grad phi* would.  The returned value L(u*, phi*) is the LP optimum.
+    g = random_small_pair(6, 8, 12, dx=0.3, dt=0.2)
+    s, _, _, _ = oracle_mod.decompose(g.pcal, g.pobs, g.dx, g.dt)
+    r = oracle_mod.solve(s, g.dx, g.dt, FIXED_BUDGET())
+    assert r.rel_res <= 1e-9
+    L0, P0 = oracle_mod.lagrangian_value(s, r.ux, r.ut, r.phi, g.dx, g.dt)
+    assert L0 == r.emd and P0 == r.primal
+    gx, gt = oracle_mod.grad(r.phi, g.dx, g.dt)
+    h = 1e-3 * max(np.abs(r.ux).max(), np.abs(r.ut).max())
+    rng = np.random.default_rng(3)
+    dirs = [(gx, gt), (-gx, -gt)] + [(rng.normal(size=s.shape), rng.normal(size=s.shape))
+                                     for _ in range(30)]
+    worst = np.inf
+    for dx_, dt_ in dirs:
+        nrm = np.sqrt(np.sum(dx_ ** 2) + np.sum(dt_ ** 2))
+        L, _ = oracle_mod.lagrangian_value(s, r.ux + h * dx_ / nrm, r.ut + h * dt_ / nrm, r.phi,
+                                           g.dx, g.dt)
+        worst = min(worst, L - L0)
+    assert worst >= -1e-9 * L0
+    cm = oracle_mod.cell_measure(g.nr, g.nt, g.dx, g.dt)
+    lp = kantorovich_lp(s, g.dx, g.dt, cm)
+    bound = 0.5 * 1e-4 * cm * float(np.sum(r.ux ** 2 + r.ut ** 2))
+    assert lp * (1 - 1e-7) <= L0 <= lp + bound * (1 + 1e-6) + 1e-7 * lp
