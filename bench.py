@@ -14,6 +14,7 @@ events (seed 3).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -66,6 +67,46 @@ def run_step(E, plan, pcal, pobs, bufs):
     return emd, info
 
 
+def fp64_reference(E, torch, pcal, pobs, desc, idx, tol, leg):
+    """EMD of gathers `idx` solved in FP64 far past the benchmark's stop rule (to the
+    residual `tol`), in resumed legs of `leg` iterations so that progress shows.
+    Returns (emd per gather, iterations, seconds, EMD change over the last leg)."""
+    import dataclasses
+    descs, parts_c, parts_o, off = [], [], [], 0
+    for k in idx:
+        nr, nt, dx, dt, o = desc[k]
+        descs.append((nr, nt, dx, dt, off))
+        parts_c.append(pcal[o:o + nr * nt])
+        parts_o.append(pobs[o:o + nr * nt])
+        off += nr * nt
+    a = torch.cat(parts_c).double().contiguous()
+    b = torch.cat(parts_o).double().contiguous()
+    p = E.SolverParams(precision=E.F64, tol_res=tol, max_iter=leg, sweeps_per_sync=256)
+    plan = E.Plan(descs, off, p)
+    t0 = time.perf_counter()
+    s, mass = E.emd_decompose(plan, a, b)
+    u = plan.empty(2)
+    emd, phi, u, info = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
+    done, prev = leg, None
+    while True:
+        torch.cuda.synchronize()
+        inf = E.info_numpy(info)
+        cur = emd.cpu().numpy().copy()
+        log(f"fp64 reference: {done} iterations, statuses {inf['status'].tolist()}, "
+            f"residual max {inf['rel_res'].max():.2e}")
+        if not (inf["status"] == E.GATHER_STATUS.index("MAX_ITER")).any() or done >= 8 * leg:
+            break
+        prev = cur
+        state = E.solver_state(plan)
+        done += leg
+        plan.set_params(dataclasses.replace(p, max_iter=done))
+        emd, phi, u, info = E.emd_pdhg_solve_resume(plan, s, state, u, phi, mass=mass)
+    el = time.perf_counter() - t0
+    change = float(np.max(np.abs(cur / prev - 1))) if prev is not None else None
+    plan.close()
+    return cur, inf, el, change
+
+
 def cpu_baseline(gathers, iters, threads):
     """The FP64 oracle, as it stands, on a bounded sample: `threads` gathers of the
     workload, `iters` fixed iterations each, one gather per host thread."""
@@ -116,7 +157,7 @@ def main():
     ap.add_argument("--ls", choices=["l2", "l1"], default="l2",
                     help="linesearch test: Euclidean (default) or the l1 norms of Algorithm 1")
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--f64-gathers", type=int, default=2,
+    ap.add_argument("--f64-gathers", type=int, default=4,
                     help="gathers of the workload solved by the plain FP64 path (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--multigrid", default="auto", metavar="FRxFT[,FRxFT...]",
@@ -124,6 +165,12 @@ def main():
                          "'auto': the measured best for the workload, 1x4,2x4 for c5, else 1x2)")
     ap.add_argument("--mg-steps", type=int, default=1, help="timed coarse-to-fine steps")
     ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--gate-gathers", type=int, default=4,
+                    help="gathers whose FP32 EMD is checked against an FP64 reference (0: skip)")
+    ap.add_argument("--gate-ref-tol", type=float, default=2e-7,
+                    help="residual the FP64 reference is solved to")
+    ap.add_argument("--c5-iters", type=int, default=300,
+                    help="fixed-budget leg on 16 gathers of 4000 x 1600 (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) 5 times, "
                          "to scale the HBM byte counters of a profiler run")
@@ -181,10 +228,44 @@ def main():
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
             "info": torch.empty(len(gathers) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
 
-    for w in range(args.warmup):
-        run_step(E, plan, pcal, pobs, bufs)
+    # Accuracy gate (untimed): the FP32 EMD of the first gathers at the stop rule
+    # against FP64 solves of them taken far past it.  If the gate fails, the stop rule
+    # is tightened before the timed steps, so the rate is measured where it holds.
+    GATE = 1e-5
+    gate = None
+    ref = None
+    if args.gate_gathers > 0:
+        idx = list(range(min(args.gate_gathers, len(gathers))))
+        ref, ref_inf, ref_s, ref_change = fp64_reference(E, torch, pcal, pobs, desc, idx,
+                                                         args.gate_ref_tol, 250000)
+        gate = {"gathers": idx, "gate": GATE, "ref": "FP64 solve of the same gathers",
+                "ref_tol_res": args.gate_ref_tol, "ref_iters": ref_inf["iters"].tolist(),
+                "ref_seconds": round(ref_s, 1), "ref_change_last_leg": ref_change}
+
+    def check_gate(emd_t, info_t):
+        e = emd_t.cpu().numpy()[:len(ref)]
+        pr = E.info_numpy(info_t)["primal"][:len(ref)]
+        err = np.abs(e / ref - 1)
+        perr = np.abs(pr / ref - 1)
+        return float(err.max()), float(perr.max()), err
+
+    for w in range(max(args.warmup, 1 if gate is not None else 0)):
+        emd_w, info_w = run_step(E, plan, pcal, pobs, bufs)
         torch.cuda.synchronize()
         log(f"warmup {w} done")
+    tightened = []
+    if gate is not None:
+        for _ in range(3):
+            err, perr, _ = check_gate(emd_w, info_w)
+            log(f"gate at residual {params.tol_res:g}: EMD rel err max {err:.2e} "
+                f"(objective of the flux alone {perr:.2e})")
+            if err <= GATE:
+                break
+            tightened.append({"tol_res": params.tol_res, "emd_rel_err_max": err})
+            params = dataclasses.replace(params, tol_res=params.tol_res * 0.3)
+            plan.set_params(params)
+            emd_w, info_w = run_step(E, plan, pcal, pobs, bufs)
+            torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -210,6 +291,13 @@ def main():
     value = cell_updates / (ms / 1e3)
     inf = E.info_numpy(info)
     emd32 = emd.cpu().numpy().copy()
+    if gate is not None:
+        err, perr, errs = check_gate(emd, info)
+        gate.update({"stop_rule": f"||div u + s||/||s|| <= {params.tol_res:g}",
+                     "emd_rel_err_vs_ref": [float(x) for x in errs], "emd_rel_err_vs_ref_max": err,
+                     "objective_rel_err_vs_ref_max": perr, "passed": err <= GATE,
+                     "tightened_from": tightened})
+        log(f"gate (timed solves): EMD rel err max {err:.2e}, objective {perr:.2e}")
     log(f"f32: {value:.3e} cell-updates/s, {ms_per_step:.1f} ms/step (wall {wall:.1f} s), "
         f"iters min/mean/max {inf['iters'].min()}/{inf['iters'].mean():.0f}/{inf['iters'].max()}, "
         f"statuses {np.bincount(inf['status'], minlength=7).tolist()}")
@@ -265,7 +353,7 @@ def main():
     if not args.no_f64:
         # the plain FP64 solve: one gather per plan (its own launch sequence), to the
         # same stop rule, on a bounded sample of the workload's gathers
-        p64 = E.SolverParams(precision=E.F64, tol_res=args.tol, max_iter=args.max_iter)
+        p64 = E.SolverParams(precision=E.F64, tol_res=params.tol_res, max_iter=args.max_iter)
         pc64 = pcal.double()
         po64 = pobs.double()
         sample = list(range(min(args.f64_gathers, len(gathers))))
@@ -288,10 +376,15 @@ def main():
             emd64[j] = float(e.cpu()[0])
             pl.close()
         rel = np.abs(emd32[sample] - emd64) / np.abs(emd64)
-        extra["plain_f64"] = {"value": cu64 / el64, "unit": "cell-updates/s", "seconds": round(el64, 2),
-                              "gathers": len(sample),
+        extra["plain_f64"] = {"what": "the same fused sweep in FP64, one gather per plan and launch "
+                                      "sequence, on the first gathers of the workload",
+                              "value": cu64 / el64, "unit": "cell-updates/s", "seconds": round(el64, 2),
+                              "gathers": len(sample), "stop_rule": f"{params.tol_res:g}",
                               "speedup_f32_batched": round(value / (cu64 / el64), 2),
                               "emd_rel_diff_f32_vs_f64_max": float(rel.max())}
+        if ref is not None:
+            m = min(len(ref), len(sample))
+            extra["plain_f64"]["emd_rel_err_vs_ref_max"] = float(np.max(np.abs(emd64[:m] / ref[:m] - 1)))
         log(f"plain f64 ({len(sample)} gathers): {cu64 / el64:.3e} cell-updates/s in {el64:.1f} s; "
             f"EMD rel diff f32 vs f64 max {rel.max():.2e}")
 
@@ -300,6 +393,48 @@ def main():
         threads = max(1, min(16, os.cpu_count() or 1))
         cpu = cpu_baseline(gathers, args.cpu_iters, threads)
         log(f"cpu oracle: {cpu['value']:.3e} cell-updates/s on {threads} threads")
+
+    if args.c5_iters > 0 and args.workload != "c5":
+        # the >2 GB workload at a fixed budget (the paper's experiments run 100-200
+        # iterations per gather): 16 gathers of 4000 x 1600, decompose -> solve ->
+        # adjoint per step, with the sweep's own roofline
+        g5, w5 = workload("c5")
+        pc5_h, po5_h, desc5 = pack_batch(g5, np.float32)
+        del g5
+        pc5 = torch.from_numpy(pc5_h).to(dev)
+        po5 = torch.from_numpy(po5_h).to(dev)
+        del pc5_h, po5_h
+        p5 = E.SolverParams(precision=E.F32, tol_res=0.0, max_iter=args.c5_iters, check_every=args.c5_iters)
+        plan5 = E.Plan(desc5, pc5.numel(), p5)
+        b5 = {"s": plan5.empty(), "phi": plan5.empty(), "psi": plan5.empty(),
+              "mass": torch.empty(len(desc5), 3, dtype=torch.float64, device=dev),
+              "emd": torch.empty(len(desc5), dtype=torch.float64, device=dev),
+              "info": torch.empty(len(desc5) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
+        run_step(E, plan5, pc5, po5, b5)  # captures the graph
+        torch.cuda.synchronize()
+        reps5, cu5, ms5, sw5 = 3, 0, 0.0, 0
+        e0.record(stream)
+        for _ in range(reps5):
+            run_step(E, plan5, pc5, po5, b5)
+            q5 = plan5.query()
+            cu5 += q5["last_cell_updates"]
+            ms5 += q5["last_sweep_ms"]
+            sw5 += q5["last_sweeps"]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        step5 = e0.elapsed_time(e1) / reps5
+        ach5 = BYTES_PER_CELL_ITER["f32"] * cu5 / (ms5 / 1e3) / 1e9
+        extra["large_fixed_budget"] = {
+            "workload": w5, "iterations": args.c5_iters, "steps": reps5,
+            "value": cu5 / reps5 / (step5 / 1e3), "unit": "cell-updates/s", "ms_per_step": round(step5, 3),
+            "roofline": {"bound": "hbm", "achieved": round(ach5, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach5 / HBM_PEAK_GBS, 4), "kernel": "k_sweep<float, false>",
+                         "launches": int(sw5), "avg_launch_us": round(ms5 * 1e3 / max(sw5, 1), 2),
+                         "algo_bytes_per_launch": int(BYTES_PER_CELL_ITER["f32"] * cu5 / max(sw5, 1))}}
+        log(f"16 x 4000 x 1600, {args.c5_iters} iterations: {step5:.1f} ms/step, sweeps at "
+            f"{ach5:.0f} GB/s ({ach5 / HBM_PEAK_GBS:.3f} of peak)")
+        plan5.close()
+        del pc5, po5, b5
 
     if args.multigrid == "auto":
         args.multigrid = "1x4,2x4" if args.workload == "c5" else "1x2"
@@ -331,6 +466,9 @@ def main():
             "fine_iters_mean": float(im["iters"].mean()), "fine_iters_max": int(im["iters"].max()),
             "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mg.last_info],
             "emd_rel_diff_vs_plain_max": float(rel_m.max())}
+        if ref is not None:
+            extra["multigrid"]["emd_rel_err_vs_ref_max"] = float(
+                np.max(np.abs(emd_m.cpu().numpy()[:len(ref)] / ref - 1)))
         log(f"coarse-to-fine {args.multigrid}: {mg_ms:.1f} ms/step ({ms_per_step / mg_ms:.2f}x), "
             f"fine iters mean {im['iters'].mean():.0f}, EMD rel diff vs plain max {rel_m.max():.2e}")
         mg.close()
@@ -340,12 +478,15 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wdesc, "gathers": len(gathers), "cells": cells,
-                      "stop_rule": f"||div u + s||/||s|| <= {args.tol}", "max_iter": args.max_iter,
+                      "stop_rule": f"||div u + s||/||s|| <= {params.tol_res:g}", "max_iter": args.max_iter,
                       "linesearch": args.ls,
                       "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
                       "tile_rows": heights if heights else (args.rows or plan.query()["rows_per_tile"]),
                       "tile_rows_per_gather": plan.gather_tiling()},
            "roofline": roofline, "cpu_baseline": cpu}
+    if gate is not None:
+        out["emd_rel_err_vs_ref_max"] = gate["emd_rel_err_vs_ref_max"]
+        out["accuracy_gate"] = gate
     out.update(extra)
     print(json.dumps(out))
     plan.close()
