@@ -136,7 +136,7 @@ def test_shift_study_against_closed_form():
     # 41 single traces, FP64 to the 1e-8 residual of the shift study: in 1D the flux
     # is fixed by the constraint, so the EMD must match the exact optimum
     gs = config1_pairs()
-    p = E.SolverParams(precision=E.F64, tol_res=1e-8, max_iter=10000000, sweeps_per_sync=4096)
+    p = E.SolverParams(precision=E.F64, tol_res=1e-8, max_iter=20000000, sweeps_per_sync=4096)
     log("41 single traces, FP64, 1e-8")
     plan, pcal, pobs, desc = make_plan(gs, p)
     emd, phi, u, info, mass, psi = _solve_all(plan, pcal, pobs)
