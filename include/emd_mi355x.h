@@ -235,6 +235,25 @@ emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out);
 emd_status emd_decompose(emd_plan* plan, const void* pcal, const void* pobs, void* s_out,
                          void* f_out, void* g_out, double* d_mass, hipStream_t stream);
 
+/* emd_decompose without a plan, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It computes what emd_decompose computes, with the same conventions
+ * and outputs, for the gathers described by the host array h_desc (validated as by
+ * emd_plan_create; the batch buffers must cover every gather's [offset, offset +
+ * nr nt)), in `precision` and `mass_mode` (the emd_params values).  It calls no
+ * allocating routine: the per-gather partial sums live in a file-scope device array
+ * of the library, EMD_NOALLOC_MAX_GATHERS x 256 x 3 doubles (384 KiB) per device,
+ * which each device holds until the process ends; more gathers than that are
+ * rejected (EMD_ERR_INVALID_ARGUMENT).  The sums are taken in another fixed order
+ * than emd_decompose's, so the two agree to the rounding of FP64 sums.  Every call
+ * rewrites all of the partial sums it reads, but all calls on one device share the
+ * array: calls that overlap on a device (other streams, other threads) race on it
+ * and must be ordered by the caller.  Never synchronises. */
+#define EMD_NOALLOC_MAX_GATHERS 64
+emd_status emd_decompose_noalloc(const emd_gather_desc* h_desc, int32_t ngather, int32_t precision,
+                                 int32_t mass_mode, const void* pcal, const void* pobs, void* s_out,
+                                 void* f_out, void* g_out, double* d_mass, hipStream_t stream);
+
 /* Solve min Phi(u) s.t. div u + s = 0 for every gather by PDHG with linesearch
  * (Algorithm 1, Section 2.2), all gathers in one batch of fused sweeps.
  *   s: source batch (from emd_decompose).

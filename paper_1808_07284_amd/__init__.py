@@ -8,7 +8,7 @@ hand-written HIP kernels; this package only marshals arguments into it.
 from ._lib import (EMDError, F32, F64, GATHER_STATUS, LS_FIXED, LS_L1, LS_L2,  # noqa: F401
                    MASS_BALANCE, MASS_NONE, MASS_UNIT)
 from .api import (INFO_DTYPE, EMDMisfit, Multigrid, Plan, SolverParams, coarse_descs,  # noqa: F401
-                  emd_adjoint_source,
+                  emd_adjoint_source, emd_decompose_noalloc,
                   emd_decompose, emd_misfit, emd_pdhg_solve, emd_pdhg_solve_replay,
                   emd_pdhg_solve_resume, info_numpy, lsd_misfit, prolong, residual_history, resolve_failed,
                   restrict, solver_state,

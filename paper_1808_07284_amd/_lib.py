@@ -31,7 +31,7 @@ EXPORTED = ["emd_params_default", "emd_plan_create", "emd_plan_destroy", "emd_pl
             "emd_plan_autotune", "emd_plan_set_history", "emd_plan_query", "emd_decompose", "emd_pdhg_solve",
             "emd_pdhg_solve_replay", "emd_solver_state", "emd_pdhg_solve_resume",
             "emd_adjoint_source", "emd_lsd_misfit", "emd_restrict", "emd_prolong",
-            "emd_status_string", "emd_last_error"]
+            "emd_decompose_noalloc", "emd_status_string", "emd_last_error"]
 
 
 class GatherDesc(C.Structure):
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.emd_lsd_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.emd_restrict.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
     lib.emd_prolong.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
+    lib.emd_decompose_noalloc.argtypes = [C.POINTER(GatherDesc), C.c_int32, C.c_int32, C.c_int32,
+                                          vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("emd_status_string", "emd_last_error"):
             getattr(lib, name).restype = st

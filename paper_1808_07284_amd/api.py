@@ -260,6 +260,35 @@ def emd_decompose(plan: Plan, pcal, pobs, s_out=None, f_out=None, g_out=None, ma
     return s_out, mass_out
 
 
+NOALLOC_MAX_GATHERS = 64
+
+
+def emd_decompose_noalloc(descs, pcal, pobs, s_out, mass_out, precision=L.F32,
+                          mass_mode=L.MASS_BALANCE, f_out=None, g_out=None):
+    """emd_decompose without a plan (the library allocates nothing; at most 64
+    gathers): descs as for Plan, every buffer caller-owned on the current device.
+    Returns (s_out, mass_out)."""
+    dtype = torch.float64 if precision == L.F64 else torch.float32
+    dev = pcal.device
+    need = max(int(off) + int(nr) * int(nt) for nr, nt, _, _, off in descs)
+    for t_, n in ((pcal, "pcal"), (pobs, "pobs"), (s_out, "s_out"), (f_out, "f_out"), (g_out, "g_out")):
+        if t_ is None:
+            continue
+        if t_.device != dev or t_.dtype != dtype or not t_.is_contiguous() or t_.numel() < need:
+            raise ValueError(f"{n}: expected a contiguous {dtype} tensor on {dev} of at least {need} elements")
+    if (mass_out.device != dev or mass_out.dtype != torch.float64 or not mass_out.is_contiguous()
+            or mass_out.numel() < 3 * len(descs)):
+        raise ValueError(f"mass_out: expected a contiguous float64 tensor of {3 * len(descs)} elements on {dev}")
+    arr = (L.GatherDesc * len(descs))()
+    for k, (nr, nt, dx, dt, off) in enumerate(descs):
+        arr[k] = L.GatherDesc(int(nr), int(nt), float(dx), float(dt), int(off))
+    with torch.cuda.device(dev):
+        L.check(L.load().emd_decompose_noalloc(arr, len(descs), int(precision), int(mass_mode), _ptr(pcal),
+                                               _ptr(pobs), _ptr(s_out), _ptr(f_out), _ptr(g_out),
+                                               _ptr(mass_out), _stream(dev)))
+    return s_out, mass_out
+
+
 def emd_pdhg_solve(plan: Plan, s, phi=None, u=None, warm_start=False, mass=None, emd_out=None,
                    info_out=None):
     """PDHG with linesearch for every gather (Algorithm 1).

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1230,6 +1231,124 @@ emd_status emd_prolong(const emd_plan* coarse, const emd_plan* fine, int32_t fr,
         a.phi_f = static_cast<double*>(phi_f);
         launch_prolong<double>(a, fine->ngather, transfer_blocks(rows), stream);
     }
+    HIP_TRY(hipGetLastError());
+    return EMD_SUCCESS;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free decompose
+//
+// emd_decompose_noalloc keeps its per-gather partial sums in this file-scope device
+// array instead of a plan's workspace: 64 gathers x 256 records x 3 doubles
+// (384 KiB), which each device the library runs on holds until the process ends.
+// Host code never passes the array's name to a kernel (in host code it stands for
+// the array, not for its device address): the address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and that
+// pointer is what the kernels receive.
+namespace {
+
+static_assert(kNdMaxGathers == EMD_NOALLOC_MAX_GATHERS, "the header states the scratch array's size");
+__device__ __align__(256) double scratch[kNdMaxGathers * kNdBlocks * 3];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (found on the first call there),
+// or NULL with the error set.
+emd_status noalloc_scratch(double** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EMD_ERR_DEVICE, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(EMD_ERR_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(EMD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return EMD_SUCCESS;
+}
+
+template <typename T>
+void noalloc_launch(const emd_gather_desc* h_desc, int32_t ngather, int32_t mass_mode, const void* pcal,
+                    const void* pobs, void* s_out, void* f_out, void* g_out, double* d_mass,
+                    double* ws, hipStream_t stream)
+{
+    NdArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.ngather = ngather;
+    a.mass_mode = mass_mode;
+    for (int g = 0; g < ngather; ++g) {
+        const emd_gather_desc& d = h_desc[g];
+        a.g[g].off = d.offset;
+        a.g[g].n = (int64_t)d.nr * d.nt;
+        a.g[g].cm = (d.nr > 1 ? d.dx : 1.0) * (d.nt > 1 ? d.dt : 1.0);
+    }
+    a.pcal = static_cast<const T*>(pcal);
+    a.pobs = static_cast<const T*>(pobs);
+    a.s_out = static_cast<T*>(s_out);
+    a.f_out = static_cast<T*>(f_out);
+    a.g_out = static_cast<T*>(g_out);
+    a.mass_out = d_mass;
+    a.scratch = ws;
+    launch_decompose_noalloc<T>(a, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+emd_status emd_decompose_noalloc(const emd_gather_desc* h_desc, int32_t ngather, int32_t precision,
+                                 int32_t mass_mode, const void* pcal, const void* pobs, void* s_out,
+                                 void* f_out, void* g_out, double* d_mass, hipStream_t stream)
+{
+    g_last_error.clear();
+    const Range range("emd_decompose_noalloc");
+    if (!h_desc) return fail(EMD_ERR_NULL_POINTER, "h_desc is NULL");
+    if (!pcal || !pobs || !s_out || !d_mass) return fail(EMD_ERR_NULL_POINTER, "pcal, pobs, s_out and d_mass are required");
+    if (s_out == pcal || s_out == pobs) return fail(EMD_ERR_INVALID_ARGUMENT, "s_out aliases an input");
+    if (ngather < 1 || ngather > kNdMaxGathers)
+        return fail(EMD_ERR_INVALID_ARGUMENT, "ngather must lie in [1, " + std::to_string(kNdMaxGathers) +
+                                                  "] (the size of the library's static scratch array)");
+    if (precision != EMD_F32 && precision != EMD_F64) return fail(EMD_ERR_INVALID_ARGUMENT, "unknown precision");
+    if (mass_mode < EMD_MASS_BALANCE || mass_mode > EMD_MASS_NONE) return fail(EMD_ERR_INVALID_ARGUMENT, "unknown mass_mode");
+    std::pair<int64_t, int64_t> spans[kNdMaxGathers];
+    for (int g = 0; g < ngather; ++g) {
+        const emd_gather_desc& d = h_desc[g];
+        char msg[160];
+        if (d.nr < 1 || d.nt < 1 || (int64_t)d.nr * d.nt > (int64_t)1 << 31) {
+            std::snprintf(msg, sizeof msg, "gather %d: nr, nt must be >= 1 and nr*nt <= 2^31", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        if (!(d.dx > 0.0) || !(d.dt > 0.0) || !std::isfinite(d.dx) || !std::isfinite(d.dt)) {
+            std::snprintf(msg, sizeof msg, "gather %d: dx and dt must be finite and > 0", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        if (d.offset < 0) {
+            std::snprintf(msg, sizeof msg, "gather %d: offset must be >= 0", g);
+            return fail(EMD_ERR_INVALID_ARGUMENT, msg);
+        }
+        spans[g] = {d.offset, d.offset + (int64_t)d.nr * d.nt};
+    }
+    std::sort(spans, spans + ngather);
+    for (int k = 1; k < ngather; ++k)
+        if (spans[k].first < spans[k - 1].second) return fail(EMD_ERR_INVALID_ARGUMENT, "gathers overlap");
+    double* ws = nullptr;
+    const emd_status st = noalloc_scratch(&ws);
+    if (st != EMD_SUCCESS) return st;
+    if (precision == EMD_F32)
+        noalloc_launch<float>(h_desc, ngather, mass_mode, pcal, pobs, s_out, f_out, g_out, d_mass, ws, stream);
+    else
+        noalloc_launch<double>(h_desc, ngather, mass_mode, pcal, pobs, s_out, f_out, g_out, d_mass, ws, stream);
     HIP_TRY(hipGetLastError());
     return EMD_SUCCESS;
 }

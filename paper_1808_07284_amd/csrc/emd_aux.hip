@@ -602,7 +602,104 @@ __global__ __launch_bounds__(64) void k_lsd_value(AuxArgs<T> a)
     if (threadIdx.x == 0) a.emd_out[g] = 0.5 * gm.cm * q[0];
 }
 
+// ------------------------------------------------------------------ plan-free decompose
+//
+// The same recombination and normalisation as k_decomp_*, for a batch described in
+// the kernel arguments, with the per-gather sums in a scratch array the caller owns.
+// Gather g is cut into kNdBlocks contiguous chunks of its nr * nt elements; block
+// (b, g) sums chunk b (threads stride through it, the four waves' sums are added in
+// order) into record (g, b), and one wave per gather adds its records in a fixed
+// order: deterministic, and every record is rewritten by every call.
+
+template <typename T>
+__device__ __forceinline__ void nd_chunk(const NdArgs<T>& a, int g, int b, int64_t& lo, int64_t& hi)
+{
+    const int64_t n = a.g[g].n;
+    const int64_t chunk = (n + kNdBlocks - 1) / kNdBlocks;
+    lo = min((int64_t)b * chunk, n);
+    hi = min(lo + chunk, n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_sums(NdArgs<T> a)
+{
+    const int g = blockIdx.y, b = blockIdx.x;
+    int64_t lo, hi;
+    nd_chunk(a, g, b, lo, hi);
+    const int64_t off = a.g[g].off;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const double pc = double(a.pcal[off + e]), po = double(a.pobs[off + e]);
+        acc[0] += fpart(pc, po);
+        acc[1] += gpart(pc, po);
+        acc[2] += pc - po;
+    }
+    __shared__ double red[4][3];
+    const int w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & (WAVE - 1)) == 0) red[w][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* rec = a.scratch + ((int64_t)g * kNdBlocks + b) * 3;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rec[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_nd_mass(NdArgs<T> a)
+{
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double* rec = a.scratch + (int64_t)g * kNdBlocks * 3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = lane; b < kNdBlocks; b += WAVE) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[q] += rec[b * 3 + q];
+    }
+    double sum[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sum[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+        a.mass_out[3 * g + 0] = a.g[g].cm * sum[0];
+        a.mass_out[3 * g + 1] = a.g[g].cm * sum[1];
+        a.mass_out[3 * g + 2] = sum[2] / double(a.g[g].n);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_source(NdArgs<T> a)
+{
+    const int g = blockIdx.y, b = blockIdx.x;
+    int64_t lo, hi;
+    nd_chunk(a, g, b, lo, hi);
+    const int64_t off = a.g[g].off;
+    const double Mf = a.mass_out[3 * g], Mg = a.mass_out[3 * g + 1], mean = a.mass_out[3 * g + 2];
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const double pc = double(a.pcal[off + e]), po = double(a.pobs[off + e]);
+        const double f = fpart(pc, po), gg = gpart(pc, po);
+        double s;
+        if (a.mass_mode == MASS_BALANCE) s = (pc - po) - mean;
+        else if (a.mass_mode == MASS_UNIT) s = (Mf > 0.0 ? f / Mf : 0.0) - (Mg > 0.0 ? gg / Mg : 0.0);
+        else s = pc - po;
+        a.s_out[off + e] = T(s);
+        if (a.f_out) a.f_out[off + e] = T(f);
+        if (a.g_out) a.g_out[off + e] = T(gg);
+    }
+}
+
 }  // namespace
+
+template <typename T>
+void launch_decompose_noalloc(const NdArgs<T>& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_nd_sums<T>, dim3(kNdBlocks, a.ngather), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_nd_mass<T>, dim3(a.ngather), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(k_nd_source<T>, dim3(kNdBlocks, a.ngather), dim3(256), 0, stream, a);
+}
 
 template <typename T>
 void launch_lsd(const AuxArgs<T>& a, int grid, hipStream_t stream)
@@ -678,7 +775,8 @@ void launch_zero_counter(int32_t* counter, hipStream_t stream)
     template void launch_adjoint<T>(const AuxArgs<T>&, int, hipStream_t);           \
     template void launch_lsd<T>(const AuxArgs<T>&, int, hipStream_t);                \
     template void launch_restrict<T>(const XferArgs<T>&, int, int, hipStream_t);     \
-    template void launch_prolong<T>(const XferArgs<T>&, int, int, hipStream_t);
+    template void launch_prolong<T>(const XferArgs<T>&, int, int, hipStream_t);     \
+    template void launch_decompose_noalloc<T>(const NdArgs<T>&, hipStream_t);
 EMD_INST(float)
 EMD_INST(double)
 #undef EMD_INST

@@ -81,6 +81,33 @@ struct XferArgs {
     T* phi_f;                  //   fine phi or NULL
 };
 
+// The plan-free decompose: gathers described in the kernel arguments (at most
+// kNdMaxGathers), per-gather partial sums in a caller-provided scratch array of
+// kNdMaxGathers * kNdBlocks * 3 doubles.
+constexpr int kNdMaxGathers = 64;
+constexpr int kNdBlocks = 256;  // partial-sum records per gather (one per block)
+
+struct NdGather {
+    int64_t off;  // element offset in the caller's batch buffers
+    int64_t n;    // nr * nt
+    double cm;    // cell measure
+};
+
+template <typename T>
+struct NdArgs {
+    int32_t ngather, mass_mode;
+    NdGather g[kNdMaxGathers];
+    const T* pcal;
+    const T* pobs;
+    T* s_out;
+    T* f_out;
+    T* g_out;
+    double* mass_out;  // [ngather][3]
+    double* scratch;   // [kNdMaxGathers][kNdBlocks][3]
+};
+
+template <typename T> void launch_decompose_noalloc(const NdArgs<T>& a, hipStream_t stream);
+
 template <typename T> void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream);
 template <typename T> void launch_restrict(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream);
 template <typename T> void launch_prolong(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream);

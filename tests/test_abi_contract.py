@@ -125,6 +125,37 @@ def test_null_pointers_are_rejected():
     assert lib.emd_status_string(1) == b"EMD_ERR_INVALID_ARGUMENT"
 
 
+def test_noalloc_decompose_rejects_bad_arguments():
+    # every case fails validation on the host, before any device call (the pointers
+    # are never dereferenced); skipped where a GPU could be reached by mistake
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L, lib = _lib()
+    D = L.GatherDesc
+    p = [C.c_void_p(0x1000 * (k + 1)) for k in range(4)]
+
+    def call(descs, n, precision=0, mode=0, ptrs=p):
+        arr = (D * len(descs))(*descs)
+        return lib.emd_decompose_noalloc(arr, n, precision, mode, ptrs[0], ptrs[1], ptrs[2], None, None,
+                                         ptrs[3], None), lib.emd_last_error()
+
+    one = [D(4, 8, 0.1, 0.1, 0)]
+    assert call(one, 1, ptrs=[None, p[1], p[2], p[3]])[0] == 2
+    assert call(one, 1, ptrs=[p[0], p[1], p[0], p[3]])[0] == 1            # s_out aliases pcal
+    st, msg = call([D(1, 4, 1.0, 1.0, 4 * k) for k in range(65)], 65)
+    assert st == 1 and b"static scratch" in msg
+    assert call(one, 0)[0] == 1
+    assert call(one, 1, precision=2)[0] == 1
+    assert call(one, 1, mode=3)[0] == 1
+    assert call([D(0, 8, 0.1, 0.1, 0)], 1)[0] == 1
+    assert call([D(4, 8, 0.0, 0.1, 0)], 1)[0] == 1
+    assert call([D(4, 8, 0.1, 0.1, -1)], 1)[0] == 1
+    assert call([D(2, 4, 1.0, 1.0, 0), D(2, 4, 1.0, 1.0, 4)], 2)[0] == 1  # overlap
+    st, _ = call(one, 1)                                                   # valid: no device here
+    assert st in (3, 4)
+
+
 def test_product_path_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1808_07284_amd")
     for dirpath, _, files in os.walk(pkg):
