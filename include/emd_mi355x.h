@@ -29,9 +29,13 @@
  *   never frees or retains it past the call.  The plan owns its workspace
  *   (padded solver state, per-gather scalars, reduction partials).
  * Streams.  Work is enqueued on `stream` (0 = the null stream).  emd_decompose
- *   and emd_adjoint_source never synchronise.  emd_pdhg_solve synchronises the
- *   stream once per `sweeps_per_sync` iterations to read the number of finished
- *   gathers (one 4-byte read), unless `max_iter` caps the solve first.
+ *   and emd_adjoint_source never synchronise.  emd_pdhg_solve (and its resume and
+ *   replay forms) synchronises the stream before its first chunk of sweeps, after
+ *   every chunk of `sweeps_per_sync` sweeps (to read the number of finished
+ *   gathers, and whenever some have finished their states, to narrow the sweeps
+ *   to the running ones) and at the end (to read the per-gather states); with
+ *   sweeps_per_sync = 0 it enqueues a fixed budget of sweeps and never
+ *   synchronises (see emd_params).
  * Errors.  A call returns EMD_SUCCESS or an error code; emd_last_error() gives a
  *   message (per thread).  Bad arguments are reported before anything is
  *   enqueued.  Numerical outcomes are per-gather statuses (EMD_GATHER_*) in the
@@ -107,7 +111,16 @@ typedef struct {
  *   precision: element type of all field buffers (EMD_F32: float fields, FP64
  *     reductions and scalars; EMD_F64: double throughout).
  *   sweeps_per_sync: iterations enqueued between reads of the finished count
- *     (even, 2..4096). */
+ *     (even, 2..4096), or 0: the fixed-budget solve, which enqueues every sweep
+ *     the budget allows (max_iter + 2, times up to max_ls_trials / 6 + 2 with the
+ *     l1 test) and reads nothing back.  The stop rule still ends each gather's
+ *     iterations on the device (its later sweeps only carry its state), and the
+ *     results are bitwise those of the chunked solve.  Such a call neither
+ *     synchronises nor allocates, so it can be captured into a HIP graph; the
+ *     graph then uses the plan's workspace, tile table and parameters as they were
+ *     at capture (keep the plan, and its tiling, while the graph may run).
+ *     emd_plan_query and emd_solver_state synchronise the device before reading
+ *     the state such a solve left. */
 typedef struct {
     double eps, xi, zeta, delta, alpha1, alpha_max_factor, tol_res, mass_tol;
     int32_t max_iter, check_every, max_ls_trials, ls_mode;

@@ -90,6 +90,8 @@ struct emd_plan {
     double* d_adj = nullptr;   // [ngather][4]
     ResumeRec* d_resume = nullptr;  // [ngather] checkpoint a resumed solve continues from
     std::vector<GState> last_state;  // per-gather state at the end of the last solve
+    bool state_on_device = false;    // the last solve (fixed budget) has not been read back
+    std::vector<int32_t> resume_iters;  // its checkpointed iteration counts (resume), or empty
     int32_t* h_done = nullptr; // pinned
     int64_t workspace_bytes = 0;
 
@@ -139,9 +141,10 @@ emd_status validate_params(const emd_params* p)
     if (p->mass_mode < EMD_MASS_BALANCE || p->mass_mode > EMD_MASS_NONE) return bad("unknown mass_mode");
     if (p->precision != EMD_F32 && p->precision != EMD_F64) return bad("unknown precision");
     // a solve reads the newest state from buffer 0, so every chunk is an even number
-    // of sweeps
-    if (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096 || (p->sweeps_per_sync & 1))
-        return bad("sweeps_per_sync must be even and lie in [2, 4096]");
+    // of sweeps; 0 selects the fixed-budget solve (no reads between sweeps)
+    if (p->sweeps_per_sync != 0 &&
+        (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096 || (p->sweeps_per_sync & 1)))
+        return bad("sweeps_per_sync must be 0, or even and in [2, 4096]");
     return EMD_SUCCESS;
 }
 
@@ -425,6 +428,28 @@ emd_status build_chains(emd_plan* plan, const std::vector<char>& sel, const Swee
     return EMD_SUCCESS;
 }
 
+// Read the per-gather state the last solve left in buffer 0 and derive the plan
+// statistics from it: cell updates = sum of nr nt times the iterations the solve ran
+// (past a resumed checkpoint's).  wait: the solve's stream is not known to be done
+// (a fixed-budget solve, possibly replayed from a caller's graph), so the device is
+// synchronised first.
+emd_status read_state(emd_plan* plan, bool wait)
+{
+    if (!plan->state_on_device) return EMD_SUCCESS;
+    if (wait) HIP_TRY(hipDeviceSynchronize());
+    std::vector<GState> st(plan->ngather);
+    HIP_TRY(hipMemcpy(st.data(), plan->d_gst, sizeof(GState) * plan->ngather, hipMemcpyDeviceToHost));
+    int64_t cu = 0;
+    for (int g = 0; g < plan->ngather; ++g) {
+        const int64_t it0 = !plan->resume_iters.empty() && st[g].status != ST_ZERO_SOURCE ? plan->resume_iters[g] : 0;
+        cu += (int64_t)plan->desc[g].nr * plan->desc[g].nt * std::max<int64_t>(st[g].iters - it0, 0);
+    }
+    plan->last_cell_updates = cu;
+    plan->last_state = st;
+    plan->state_on_device = false;
+    return EMD_SUCCESS;
+}
+
 // Enqueue `count` (even) sweeps starting at parity 0.  Uses a captured graph of
 // sweeps_per_sync launches per chain when count equals that chunk size.
 template <typename T>
@@ -508,16 +533,42 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
 
     const int ls_mode = replay ? LS_REPLAY : plan->params.ls_mode;
     const SweepArgs<T> sa = sweep_args<T>(plan, scalars(plan, ls_mode, replay, ld_replay));
-    Chains<T> ch;
-    std::memset(&ch, 0, sizeof(ch));
-    std::vector<char> sel(plan->ngather, 1);
-    emd_status cst = build_chains<T>(plan, sel, sa, ch, stream);
-    if (cst != EMD_SUCCESS) return cst;
     const int chunk = plan->params.sweeps_per_sync;
     // a gather needs iters + 1 sweeps, the last one applying the final dual step;
     // the l1 test may add an evaluation sweep per NL1 failed backtracking trials
     const int64_t evals = ls_mode == LS_L1 ? plan->params.max_ls_trials / NL1 + 1 : 0;
     const int64_t max_sweeps = round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
+    plan->resume_iters.clear();
+    if (h_resume)
+        for (int g = 0; g < plan->ngather; ++g) plan->resume_iters.push_back(h_resume[g].iters);
+    if (chunk == 0) {
+        // Fixed budget: every sweep the budget allows goes on the stream, over the full
+        // tile table, with nothing read back (the stop rule still ends each gather's
+        // iterations on the device; its later sweeps only carry its state).  The same
+        // tiles and slots as the chunked solve, so the same bits.  Nothing here
+        // synchronises or allocates, so a caller can capture the call into a graph.
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(stream, &cap));
+        const bool timed = cap == hipStreamCaptureStatusNone;
+        if (timed) HIP_TRY(hipEventRecord(plan->ev0, stream));
+        for (int64_t n = 0; n < max_sweeps; ++n) launch_sweep<T>(sa, (int)(n & 1), plan->grid, stream);
+        if (timed) HIP_TRY(hipEventRecord(plan->ev1, stream));
+        HIP_TRY(hipGetLastError());
+        plan->last_sweeps = max_sweeps;
+        plan->last_rebuilds = 0;
+        plan->timing_valid = timed;
+        a.gst = plan->d_gst;
+        launch_finalize<T>(a, plan->grid, stream);
+        launch_copy_out<T>(a, plan->grid, stream);
+        HIP_TRY(hipGetLastError());
+        plan->state_on_device = true;  // read back when the state or statistics are asked for
+        return EMD_SUCCESS;
+    }
+    Chains<T> ch;
+    std::memset(&ch, 0, sizeof(ch));
+    std::vector<char> sel(plan->ngather, 1);
+    emd_status cst = build_chains<T>(plan, sel, sa, ch, stream);
+    if (cst != EMD_SUCCESS) return cst;
     int64_t sweeps = 0;
     // Finished gathers leave the sweep's tile tables: once the running gathers hold at
     // most 15/16 of the tables' cells, the chains are rebuilt from them alone and spread
@@ -577,18 +628,9 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     launch_copy_out<T>(a, plan->grid, stream);
     HIP_TRY(hipGetLastError());
 
-    // cell updates of the solve, for the plan statistics
-    std::vector<GState> st(plan->ngather);
-    HIP_TRY(hipMemcpyAsync(st.data(), plan->d_gst, sizeof(GState) * plan->ngather, hipMemcpyDeviceToHost, stream));
+    plan->state_on_device = true;
     HIP_TRY(hipStreamSynchronize(stream));
-    int64_t cu = 0;
-    for (int g = 0; g < plan->ngather; ++g) {
-        const int64_t it0 = h_resume && st[g].status != ST_ZERO_SOURCE ? h_resume[g].iters : 0;
-        cu += (int64_t)plan->desc[g].nr * plan->desc[g].nt * std::max<int64_t>(st[g].iters - it0, 0);
-    }
-    plan->last_cell_updates = cu;
-    plan->last_state = st;
-    return EMD_SUCCESS;
+    return read_state(plan, false);
 }
 
 }  // namespace
@@ -916,6 +958,8 @@ emd_status emd_plan_query(const emd_plan* plan, emd_plan_stats* out)
 {
     g_last_error.clear();
     if (!plan || !out) return fail(EMD_ERR_NULL_POINTER, "plan or out is NULL");
+    const emd_status rs = read_state(const_cast<emd_plan*>(plan), true);
+    if (rs != EMD_SUCCESS) return rs;
     std::memset(out, 0, sizeof(*out));
     out->ngather = plan->ngather;
     out->tiles = plan->ntiles;
@@ -1016,6 +1060,8 @@ emd_status emd_solver_state(const emd_plan* plan, emd_gather_state* h_state)
 {
     g_last_error.clear();
     if (!plan || !h_state) return fail(EMD_ERR_NULL_POINTER, "plan or h_state is NULL");
+    const emd_status rs = read_state(const_cast<emd_plan*>(plan), true);
+    if (rs != EMD_SUCCESS) return rs;
     if (plan->last_state.size() != (size_t)plan->ngather)
         return fail(EMD_ERR_INVALID_ARGUMENT, "the plan has not solved yet");
     for (int g = 0; g < plan->ngather; ++g) {

@@ -82,6 +82,8 @@ def _create(L, lib, descs, batch_len, **over):
     ([(2, 5, 1.0, 1.0, 0)], 10, {"mass_mode": 3}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 1}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 3}, 1),  # chunks hold whole sweep pairs
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": -2}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 4098}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 3}, 1),         # unknown linesearch test
     # a field region of a gather (nr rows of nt rounded up to 32) may not pass 1 GiB
     ([(16384, 16385, 1.0, 1.0, 0)], 16384 * 16385, {}, 1),
