@@ -120,11 +120,16 @@ typedef struct {
  *     graph then uses the plan's workspace, tile table and parameters as they were
  *     at capture (keep the plan, and its tiling, while the graph may run).
  *     emd_plan_query and emd_solver_state synchronise the device before reading
- *     the state such a solve left. */
+ *     the state such a solve left.
+ *   iters_per_sweep: 1 (or 0): one PDHG iteration per sweep of the fields; 2: with
+ *     EMD_LS_FIXED only, two iterations per sweep (one HBM pass reads u, phi, s and
+ *     writes u, phi for two iterations; the fields are bitwise those of one
+ *     iteration per sweep), with check_every even: the stop rule is checked on even
+ *     iteration counts. */
 typedef struct {
     double eps, xi, zeta, delta, alpha1, alpha_max_factor, tol_res, mass_tol;
     int32_t max_iter, check_every, max_ls_trials, ls_mode;
-    int32_t mass_mode, precision, sweeps_per_sync, reserved;
+    int32_t mass_mode, precision, sweeps_per_sync, iters_per_sweep;
 } emd_params;
 
 /* Per-gather result (device array written by emd_pdhg_solve).

@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("tol_res", C.c_double), ("mass_tol", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("max_ls_trials", C.c_int32), ("ls_mode", C.c_int32),
                 ("mass_mode", C.c_int32), ("precision", C.c_int32),
-                ("sweeps_per_sync", C.c_int32), ("reserved", C.c_int32)]
+                ("sweeps_per_sync", C.c_int32), ("iters_per_sweep", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

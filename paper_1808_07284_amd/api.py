@@ -44,12 +44,12 @@ class SolverParams:
     mass_mode: int = L.MASS_BALANCE
     precision: int = L.F32
     sweeps_per_sync: int = 64
+    iters_per_sweep: int = 1
 
     def to_c(self) -> L.Params:
         p = L.Params()
         for f in fields(self):
             setattr(p, f.name, getattr(self, f.name))
-        p.reserved = 0
         return p
 
     @classmethod

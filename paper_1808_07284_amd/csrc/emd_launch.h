@@ -21,7 +21,8 @@ struct SweepArgs {
     double* part[2];       // [slots][NPART or NPART_L1] partial sums, by sweep parity
     GState* gst[2];        // [ngather], by sweep parity
     int32_t* done;         // gathers that have finished
-    int32_t l1, pad;       // 1: the l1 form of the linesearch test
+    int32_t l1;            // 1: the l1 form of the linesearch test
+    int32_t two;           // 1: fixed-step PDHG, two iterations per sweep (k_sweep2)
     SolveScalars sc;
 };
 

@@ -1086,10 +1086,385 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
     }
 }
 
+// ======================================================================================
+// Plain PDHG with the fixed steps alpha_1, beta_1 = delta alpha_1 and theta = 1 (the
+// primal and dual updates of Section 2.2 before the linesearch is introduced), two
+// iterations per HBM pass.  With no linesearch nothing global sits between two
+// iterations, so one sweep takes (u_k, phi_k) to (u_{k+2}, phi_{k+2}):
+//   u_{k+1}   = shrink(u_k + alpha grad phi_k, alpha) / (1 + eps alpha)        (P1)
+//   phi_{k+1} = phi_k + beta (A_{k+1} + (A_{k+1} - A_k)),  A_m = div u_m + s     (D1)
+//   u_{k+2}   = shrink(u_{k+1} + alpha grad phi_{k+1}, alpha) / (1 + eps alpha) (P2)
+//   phi_{k+2} = phi_{k+1} + beta (A_{k+2} + (A_{k+2} - A_{k+1}))              (D2)
+// (A + (A - A') = div(2 u - u') + s: the dual step at ubar = 2 u_{m+1} - u_m.)  The
+// state is (u, phi) only: each A is recomputed from its flux, with the operands and
+// operations of the one-iteration sweep (which stores A_k as R), so the fields are
+// bitwise those of that sweep with fixed steps.  A sweep reads u, phi, s (16 bytes per
+// cell in FP32) and writes u, phi (12 bytes) for two iterations, against 36 bytes per
+// iteration for the linesearch sweep.
+//
+// The dependency cone grows by one row and one sample per stage: a tile loads two
+// rows above and two below its own rows, and its halo lanes (0 and 57, four samples
+// each) cover the two samples either way.  The wave marches down; at step i (row i
+// just loaded) it forms P1 of row i, A_k, A_{k+1} and D1 of row i - 1, P2 of row
+// i - 1, then A_{k+2} and D2 of row i - 2.  Loaded rows sit in register sets indexed
+// by row mod 4 (the next row loads into the set of row i - 3), computed rows in sets
+// indexed by row mod 2; the loop is unrolled by four so every index is static.
+// ======================================================================================
+
+struct Decision2 {
+    double alpha, beta;
+    int steps;  // PDHG iterations this sweep applies to the gather (0: none)
+};
+
+// The gather's decision at the start of a sweep: the stop rule on the sums of the
+// previous sweep (which describe u_k, the flux this sweep reads), then how many
+// iterations this sweep runs: two, or one to bring an odd count (a resumed
+// checkpoint) back to even, or to end at max_iter.  Checks fall on even counts.
+template <typename T>
+__device__ Decision2 decide_fixed2(const SweepArgs<T>& a, int p, int g, const GatherMeta& gm, bool writer,
+                                   int pb, int w, double* red)
+{
+    const GState* __restrict__ sin = a.gst[p] + g;
+    GState* __restrict__ sout = a.gst[p ^ 1] + g;
+    GState st = *sin;
+    const SolveScalars& sc = a.sc;
+    Decision2 d;
+    d.alpha = st.alpha;
+    d.beta = sc.delta * st.alpha;
+    d.steps = 0;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (st.status != ST_RUNNING) {
+        if (writer && lane == 0) *sout = st;
+        return d;
+    }
+    int status = ST_RUNNING;
+    if (st.started) {
+        double q[NPART];
+        decision_sums<NPART>(a.part[p] + (int64_t)gm.tile_base * NPART, gm.ntiles, w, red, q);
+        const double aa = q[0], l1 = q[6], l2 = q[7];
+        if (!(isfinite(aa) && isfinite(l1) && isfinite(l2))) {
+            status = ST_NONFINITE;
+        } else {
+            st.rel_res = sqrt(aa) / st.snorm;
+            st.emd = gm.cm * (l1 + 0.5 * sc.eps * l2);
+            st.transport = gm.cm * l1;
+            if (sc.hist && writer && lane == 0 && st.iters % sc.check_every == 0)
+                sc.hist[(int64_t)g * sc.hist_cap + (st.iters / sc.check_every - 1) % sc.hist_cap] = st.rel_res;
+            if (st.iters % sc.check_every == 0 && st.rel_res <= sc.tol_res) status = ST_CONVERGED;
+            else if (st.iters >= sc.max_iter) status = ST_MAX_ITER;
+        }
+    }
+    if (status != ST_RUNNING) {
+        // u_k and phi_k are this sweep's inputs
+        st.ubuf = pb;
+        st.phibuf = pb;
+        st.status = status;
+        if (writer && lane == 0) {
+            *sout = st;
+            atomicAdd(a.done, 1);
+        }
+        return d;
+    }
+    st.started = 1;
+    int steps = (st.iters & 1) ? 1 : 2;
+    if (steps > sc.max_iter - st.iters) steps = max(sc.max_iter - st.iters, 1);
+    st.iters += steps;
+    st.ubuf = pb ^ 1;
+    st.phibuf = pb ^ 1;
+    if (writer && lane == 0) *sout = st;
+    d.steps = steps;
+    return d;
+}
+
+template <typename T, bool EDGE>
+struct Pipe2 {
+    static constexpr int V = Vec<T>::N;
+    TileCtx<T> c;
+    int iend;                                // last step (row index; past nr: virtual rows)
+    T LX[4][V], LT[4][V], LP[4][V], LS[4][V];  // u^x_k, u^t_k, phi_k, s of loaded rows, by row mod 4
+    T P1X[2][V], P1T[2][V];                  // u_{k+1}: rows i (set i & 1) and i - 1
+    T A1[2][V], D1[2][V];                    // A_{k+1}, phi_{k+1}: rows i - 1 and i - 2
+    T P2X[2][V], P2T[2][V];                  // u_{k+2}: rows i - 1 and i - 2
+    double aa, l1, l2;
+
+    __device__ explicit Pipe2(const TileCtx<T>& ctx) : c(ctx)
+    {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            zero(LX[b]); zero(LT[b]); zero(LP[b]); zero(LS[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            zero(P1X[b]); zero(P1T[b]); zero(A1[b]); zero(D1[b]); zero(P2X[b]); zero(P2T[b]);
+        }
+        aa = l1 = l2 = 0.0;
+    }
+
+    __device__ __forceinline__ void load(int i, T (&ux)[V], T (&ut)[V], T (&ph)[V], T (&sv)[V])
+    {
+        const uint32_t o = i <= c.ilast ? c.vb_ld + (uint32_t)i * c.row_bytes : OOB;
+        bload(c.uxi, o, ux);
+        bload(c.uti, o, ut);
+        bload(c.phi_i, o, ph);
+        bload(c.si, o, sv);
+    }
+
+    __device__ __forceinline__ bool own(int m) const { return m >= c.r0 && m < c.rend; }
+    __device__ __forceinline__ uint32_t store_off(int m) const
+    {
+        return c.vb_st + (own(m) ? (uint32_t)m * c.row_bytes : OOB);
+    }
+
+    // the shrink step of the primal update on one row: u' = prox(u + alpha grad phi),
+    // grad the backward difference (phi of the row above: pu, weight wgx)
+    __device__ __forceinline__ void prox_row(const T (&ux)[V], const T (&ut)[V], const T (&ph)[V],
+                                             const T (&pu)[V], bool has_prev, T (&ox)[V], T (&ot)[V]) const
+    {
+        const T ph_prev = __shfl_up(ph[V - 1], 1, WAVE);
+        const T wgx = has_prev ? c.idx : T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const T gx = (ph[k] - pu[k]) * wgx;
+            const T pprev = (k > 0) ? ph[(k + V - 1) % V] : ph_prev;
+            T gt = (ph[k] - pprev) * c.idt;
+            if constexpr (EDGE) gt = c.jgt0[k] ? gt : T(0);
+            ox[k] = shrink_scaled(fma(c.alpha, gx, ux[k]), c.alpha, c.inv);
+            ot[k] = shrink_scaled(fma(c.alpha, gt, ut[k]), c.alpha, c.inv);
+        }
+    }
+
+    __device__ __forceinline__ void dual_row(const T (&an)[V], const T (&r)[V], const T (&ph)[V], T (&out)[V]) const
+    {
+#pragma unroll
+        for (int k = 0; k < V; ++k) out[k] = fma(c.beta, fma(c.theta, an[k] - r[k], an[k]), ph[k]);
+    }
+
+    __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, const T (&x)[V]) const
+    {
+        T w[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) w[k] = (!EDGE || c.inb[k]) ? x[k] : T(0);
+        bstore(r, off, w);
+    }
+
+    // sums for the stop rule: sum |u|, sum u^2 of a flux row, <A, A> of a residual row
+    __device__ __forceinline__ void sum_flux(int m, const T (&ux)[V], const T (&ut)[V])
+    {
+        if (!(own(m) && c.lane_out)) return;
+        T s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (!EDGE || c.inb[k]) {
+                s1 += fabs(ux[k]) + fabs(ut[k]);
+                s2 = fma(ux[k], ux[k], fma(ut[k], ut[k], s2));
+            }
+        }
+        l1 += double(s1);
+        l2 += double(s2);
+    }
+    __device__ __forceinline__ void sum_res(int m, const T (&a)[V])
+    {
+        if (!(own(m) && c.lane_out)) return;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (EDGE && !c.inb[k]) continue;
+            const double av = double(a[k]);
+            aa = fma(av, av, aa);
+        }
+    }
+
+    // step on row i; S = (i - ibeg) mod 4; TWO: two iterations (else one)
+    template <int S, bool TWO>
+    __device__ __forceinline__ void step(int i)
+    {
+        constexpr int C = S, PV = (S + 3) & 3, PV2 = (S + 2) & 3, NX = (S + 1) & 3;
+        constexpr int P = S & 1, Q = P ^ 1;
+        load(i + 1, LX[NX], LT[NX], LP[NX], LS[NX]);
+        // P1 of row i
+        prox_row(LX[C], LT[C], LP[C], LP[PV], i > 0, P1X[P], P1T[P]);
+        // A_k and A_{k+1} of row i - 1, then D1
+        const int m = i - 1;
+        const bool nxt = i < c.nr, prv = m > 0;
+        T a0[V], a1[V];
+        div_row<T, EDGE>(c, nxt, prv, LX[PV], LX[C], LT[PV], __shfl_down(LT[PV][0], 1, WAVE), LS[PV], a0);
+        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], __shfl_down(P1T[Q][0], 1, WAVE), LS[PV], a1);
+        dual_row(a1, a0, LP[PV], D1[Q]);
+        if constexpr (!TWO) {
+            // one iteration: u_{k+1} of row i - 1 and phi_{k+1} of row i - 1 are the outputs
+            store(c.uxo, store_off(m), P1X[Q]);
+            store(c.uto, store_off(m), P1T[Q]);
+            store(c.phio, store_off(m), D1[Q]);
+            sum_flux(m, P1X[Q], P1T[Q]);
+            sum_res(m, a1);
+#pragma unroll
+            for (int k = 0; k < V; ++k) A1[Q][k] = a1[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k) A1[Q][k] = a1[k];
+            // P2 of row i - 1 (phi_{k+1} of rows i - 1 and i - 2)
+            prox_row(P1X[Q], P1T[Q], D1[Q], D1[P], m > 0, P2X[Q], P2T[Q]);
+            store(c.uxo, store_off(m), P2X[Q]);
+            store(c.uto, store_off(m), P2T[Q]);
+            sum_flux(m, P2X[Q], P2T[Q]);
+            // A_{k+2} and D2 of row i - 2
+            const int m2 = i - 2;
+            T a2[V], d2[V];
+            div_row<T, EDGE>(c, i - 1 < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], __shfl_down(P2T[P][0], 1, WAVE),
+                             LS[PV2], a2);
+            dual_row(a2, A1[P], D1[P], d2);
+            store(c.phio, store_off(m2), d2);
+            sum_res(m2, a2);
+        }
+    }
+
+    template <bool TWO>
+    __device__ __forceinline__ void run()
+    {
+        load(c.ibeg, LX[0], LT[0], LP[0], LS[0]);
+        int i = c.ibeg;
+        for (; i + 3 <= iend; i += 4) {
+            step<0, TWO>(i);
+            step<1, TWO>(i + 1);
+            step<2, TWO>(i + 2);
+            step<3, TWO>(i + 3);
+        }
+        if (i <= iend) {
+            step<0, TWO>(i++);
+            if (i <= iend) {
+                step<1, TWO>(i++);
+                if (i <= iend) step<2, TWO>(i++);
+            }
+        }
+    }
+};
+
+template <typename T, bool EDGE>
+__device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
+                            double* red)
+{
+    constexpr int V = Vec<T>::N;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int q = p ^ 1, qb = pb ^ 1;
+    TileCtx<T> c;
+    c.nr = gm.nr;
+    c.ld = gm.ld;
+    const int nt = gm.nt;
+    c.r0 = tl.r0;
+    c.rend = min(tl.r0 + gm.rows, gm.nr);
+    c.ibeg = max(tl.r0 - 2, 0);
+    c.ilast = min(c.rend + 1, gm.nr - 1);  // last row loaded (two below the strip)
+    const int j0 = tl.c0 - V + V * lane;
+    const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
+    c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int j = j0 + k;
+        c.inb[k] = (j >= 0) && (j < nt);
+        c.jgt0[k] = j > 0;
+        c.jlt[k] = j + 1 < nt;
+    }
+    c.idx = T(1.0 / gm.dx);
+    c.idt = T(1.0 / gm.dt);
+    c.row_bytes = (uint32_t)(gm.ld * sizeof(T));
+    c.vb_ld = lane_load ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    c.vb_st = c.lane_out ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    const int bytes = (int)((int64_t)gm.nr * gm.ld * sizeof(T));
+    auto rs = [&](const T* f) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f + gm.poff), 0, bytes, 0x00020000);
+    };
+    c.uxi = rs(a.ux[pb]);
+    c.uti = rs(a.ut[pb]);
+    c.phi_i = rs(a.phi[pb]);
+    c.si = rs(a.s);
+    c.uxo = rs(a.ux[qb]);
+    c.uto = rs(a.ut[qb]);
+    c.phio = rs(a.phi[qb]);
+    c.ri = c.si;
+    c.ro = c.phio;
+
+    const Decision2 d = decide_fixed2<T>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
+    if (d.steps == 0) return;
+    c.beta = T(d.beta);
+    c.theta = T(1.0);
+    c.alpha = T(d.alpha);
+    c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    Pipe2<T, EDGE> P(c);
+    double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
+    if (d.steps == 2) {
+        // the last own row's D2 needs the step two rows below it (rows past the grid
+        // are virtual: nothing is loaded there and their weights are zero)
+        P.iend = c.rend + 1;
+        P.template run<true>();
+    } else {
+        P.iend = c.rend;
+        P.template run<false>();
+    }
+    double r[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) r[m] = 0.0;
+    r[0] = wave_sum(P.aa);
+    r[6] = wave_sum(P.l1);
+    r[7] = wave_sum(P.l2);
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) dst[m] = r[m];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
+{
+    constexpr int V = Vec<T>::N;
+    constexpr int WPB = 256 / WAVE;
+    __shared__ double red[WPB * NPART];
+    const int w = uniform((int)threadIdx.x / WAVE);
+    const int first = uniform(xcd_logical_block() * WPB);
+    const int tid = first + w;
+    if (tid >= a.ntiles) return;
+    // the four waves of a block on one running gather share its decision sums (as in
+    // k_sweep; every wave of such a block reaches the one barrier)
+    int gb = -1;
+    bool split = first + WPB <= a.ntiles;
+    for (int k = 0; k < WPB && split; ++k) {
+        const int gk = uniform(a.tiles[first + k].g);
+        if (gk < 0) continue;
+        if (gb < 0) gb = gk;
+        else if (gk != gb) split = false;
+    }
+    if (gb < 0) split = false;
+    if (split) {
+        const GState* sb = a.gst[parity] + gb;
+        split = uniform(sb->status) == ST_RUNNING && uniform(sb->started) != 0;
+    }
+    const Tile tl = a.tiles[tid];
+    const int g = uniform(tl.g);
+    if (g < 0) {
+        if (split) {
+            const GatherMeta mb = a.meta[gb];
+            double s[NPART];
+            decision_sums<NPART>(a.part[parity] + (int64_t)mb.tile_base * NPART, mb.ntiles, w, red, s);
+        }
+        return;
+    }
+    double* const xred = split ? red : nullptr;
+    const GatherMeta gm = a.meta[g];
+    const GState* gs = a.gst[parity] + g;
+    if (gs->status != ST_RUNNING) {
+        if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0) a.gst[parity ^ 1][g] = *gs;
+        return;
+    }
+    const int pb = parity;
+    const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
+    if (edge) sweep_tile2<T, true>(a, tl, gm, parity, pb, w, xred);
+    else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred);
+}
+
 template <typename T>
 void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream)
 {
-    if (a.l1)
+    if (a.two)
+        hipLaunchKernelGGL((k_sweep2<T>), dim3(grid), dim3(256), 0, stream, a, parity);
+    else if (a.l1)
         hipLaunchKernelGGL((k_sweep<T, true>), dim3(grid), dim3(256), 0, stream, a, parity);
     else
         hipLaunchKernelGGL((k_sweep<T, false>), dim3(grid), dim3(256), 0, stream, a, parity);
