@@ -169,6 +169,8 @@ def main():
                     help="gathers whose FP32 EMD is checked against an FP64 reference (0: skip)")
     ap.add_argument("--gate-ref-tol", type=float, default=2e-7,
                     help="residual the FP64 reference is solved to")
+    ap.add_argument("--fixed-steps", type=int, default=1,
+                    help="timed steps of plain fixed-step PDHG, two iterations per sweep (0: skip)")
     ap.add_argument("--c5-iters", type=int, default=300,
                     help="fixed-budget leg on 16 gathers of 4000 x 1600 (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -393,6 +395,49 @@ def main():
         threads = max(1, min(16, os.cpu_count() or 1))
         cpu = cpu_baseline(gathers, args.cpu_iters, threads)
         log(f"cpu oracle: {cpu['value']:.3e} cell-updates/s on {threads} threads")
+
+    if args.fixed_steps > 0:
+        # Plain PDHG with the fixed steps alpha_1, beta_1 = delta alpha_1 (Section 2.2
+        # before the linesearch): no per-iteration decision, so one sweep runs two
+        # iterations (read u, phi, s; write u, phi: 28 B per cell per sweep), to the
+        # same stop rule, with its own roofline and accuracy against the reference
+        pf = dataclasses.replace(params, ls_mode=E.LS_FIXED, iters_per_sweep=2, max_iter=4 * args.max_iter)
+        planf = E.Plan(desc, len(pcal_h), pf)
+        if rows:
+            planf.set_gather_tiling(rows)
+        run_step(E, planf, pcal, pobs, bufs)  # captures the graph
+        torch.cuda.synchronize()
+        cuf, msf, swf = 0, 0.0, 0
+        e0.record(stream)
+        for _ in range(args.fixed_steps):
+            emd_f, info_f = run_step(E, planf, pcal, pobs, bufs)
+            qf = planf.query()
+            cuf += qf["last_cell_updates"]
+            msf += qf["last_sweep_ms"]
+            swf += qf["last_sweeps"]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        stepf = e0.elapsed_time(e1) / args.fixed_steps
+        inff = E.info_numpy(info_f)
+        # algorithmic bytes: 28 per cell per sweep of two iterations (14 per iteration)
+        achf = 14 * cuf / (msf / 1e3) / 1e9
+        extra["plain_pdhg_two_iterations_per_sweep"] = {
+            "what": "plain PDHG with fixed steps, two iterations per HBM pass, FP32, same stop rule",
+            "value": cuf / args.fixed_steps / (stepf / 1e3), "unit": "cell-updates/s",
+            "ms_per_step": round(stepf, 3), "speedup_vs_linesearch_step": round(ms_per_step / stepf, 3),
+            "iters_mean": float(inff["iters"].mean()), "iters_max": int(inff["iters"].max()),
+            "statuses": np.bincount(inff["status"], minlength=7).tolist(),
+            "roofline": {"bound": "hbm", "achieved": round(achf, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achf / HBM_PEAK_GBS, 4), "kernel": "k_sweep2<float>",
+                         "launches": int(swf), "avg_launch_us": round(msf * 1e3 / max(swf, 1), 2),
+                         "algo_bytes_per_launch": int(14 * cuf / max(swf, 1))}}
+        if ref is not None:
+            ef = emd_f.cpu().numpy()[:len(ref)]
+            extra["plain_pdhg_two_iterations_per_sweep"]["emd_rel_err_vs_ref_max"] = float(
+                np.max(np.abs(ef / ref - 1)))
+        log(f"fixed steps, two iterations per sweep: {stepf:.1f} ms/step ({ms_per_step / stepf:.2f}x the "
+            f"linesearch), iters mean {inff['iters'].mean():.0f}, sweeps at {achf:.0f} GB/s")
+        planf.close()
 
     if args.c5_iters > 0 and args.workload != "c5":
         # the >2 GB workload at a fixed budget (the paper's experiments run 100-200
