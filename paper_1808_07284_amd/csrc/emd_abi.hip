@@ -49,11 +49,11 @@ struct Range {
     Range& operator=(const Range&) = delete;
 };
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = tiling::kWavesPerBlock;
 constexpr int kDefaultRows = 16;
 constexpr int kChains = 2;  // independent chains of sweep launches per captured chunk
 
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+using tiling::round_up;
 
 }  // namespace
 
@@ -163,102 +163,31 @@ void destroy_graph(emd_plan* plan)
     plan->graph_chunk = 0;
 }
 
-// Tile table.  A gather is cut into row strips of `rows` receivers by time tiles of
-// 56 * vec samples; its tiles own a contiguous range of partial-sum slots
-// [tile_base, tile_base + ntiles).  The table order serves the caches: the batch's
-// strips (gather-major) are split into 8 contiguous runs of equal cell count, one
-// per XCD (block b runs on XCD b % 8 and the kernel maps it to logical block
-// (b % 8) * per + b / 8, see xcd_logical_block), and inside a run the tiles go
-// gather by gather, strip by strip: strips k and k + 1 of a gather start at about
-// the same time and march in opposite directions (the sweep's even strips go down,
-// odd strips up), so both read the rows they share at about the same moment and
-// the second read hits that XCD's L2.  The four waves of a block are neighbours in
-// time.  Runs are padded to equal length with empty tiles.
-// Lay out the tiles of the selected gathers (sel[g] != 0): their strips, gather-
-// major, are cut into kXcd runs of about equal cells, padded to a common length
-// that is a multiple of the block size.
+// The tile table of the selected gathers, laid out over the XCDs (emd_tiling.h).
 std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& sel)
 {
-    constexpr int kXcd = 8;
-    const int span = OUT_LANES * plan->vec;
-    const std::vector<GatherMeta>& meta = plan->h_meta;
-    const std::vector<int>& ntt = plan->h_ntt;
-    const std::vector<int>& nst = plan->h_nst;
-    struct Strip { int g, st; int64_t cells; };
-    std::vector<Strip> strips;
-    int64_t total = 0;
-    for (int g = 0; g < plan->ngather; ++g) {
-        if (!sel[g]) continue;
-        for (int st = 0; st < nst[g]; ++st) {
-            const int64_t c = (int64_t)std::min(meta[g].rows, meta[g].nr - st * meta[g].rows) * meta[g].nt;
-            strips.push_back(Strip{g, st, c});
-            total += c;
-        }
-    }
-    std::vector<std::vector<Tile>> runs(kXcd);
-    size_t s0 = 0;
-    int64_t acc = 0;
-    for (int x = 0; x < kXcd; ++x) {
-        const int64_t goal = total * (x + 1) / kXcd;
-        size_t s1 = s0;
-        while (s1 < strips.size() && (x == kXcd - 1 || acc + strips[s1].cells / 2 < goal)) acc += strips[s1++].cells;
-        // gather by gather, strip by strip: a strip's neighbours are dispatched right
-        // after it, while the rows they share are still in this XCD's L2
-        for (size_t s = s0; s < s1; ++s) {
-            const int g = strips[s].g, st = strips[s].st;
-            for (int tt = 0; tt < ntt[g]; ++tt)
-                runs[x].push_back(Tile{g, st * meta[g].rows, tt * span, meta[g].tile_base + st * ntt[g] + tt});
-        }
-        s0 = s1;
-    }
-    size_t run_len = 0;
-    for (auto& r : runs) run_len = std::max(run_len, r.size());
-    run_len = (size_t)round_up((int64_t)std::max<size_t>(run_len, 1), kWavesPerBlock);
-    std::vector<Tile> tiles;
-    tiles.reserve(run_len * kXcd);
-    for (auto& r : runs) {
-        tiles.insert(tiles.end(), r.begin(), r.end());
-        tiles.resize(tiles.size() + (run_len - r.size()), Tile{-1, 0, 0, 0});
-    }
-    return tiles;
+    tiling::Layout L;
+    L.meta = plan->h_meta;
+    L.ntt = plan->h_ntt;
+    L.nst = plan->h_nst;
+    return tiling::layout_tiles(L, OUT_LANES * plan->vec, sel);
 }
 
 emd_status build_tiles(emd_plan* plan)
 {
     const int span = OUT_LANES * plan->vec;
-    std::vector<GatherMeta> meta(plan->ngather);
-    std::vector<int> ntt(plan->ngather), nst(plan->ngather);
-    int64_t poff = 0;
-    int32_t slots = 0;
+    std::vector<tiling::GatherIn> gin(plan->ngather);
     for (int g = 0; g < plan->ngather; ++g) {
         const emd_gather_desc& d = plan->desc[g];
-        GatherMeta& m = meta[g];
-        m.nr = d.nr;
-        m.nt = d.nt;
-        // rows start on 128-byte lines, so each wave's 896-byte output window is
-        // exactly seven whole lines
-        m.ld = (int32_t)round_up(d.nt, 32);
-        m.poff = poff;
-        m.uoff = d.offset;
-        m.dx = d.dx;
-        m.dt = d.dt;
-        m.cm = (d.nr > 1 ? d.dx : 1.0) * (d.nt > 1 ? d.dt : 1.0);
-        double lam = 0.0;
-        if (d.nr > 1) lam += 4.0 / (d.dx * d.dx);
-        if (d.nt > 1) lam += 4.0 / (d.dt * d.dt);
-        m.alpha1 = plan->params.alpha1 > 0.0 ? plan->params.alpha1
-                                             : (lam > 0.0 ? 1.0 / std::sqrt(plan->params.delta * lam) : 1.0);
-        ntt[g] = (d.nt + span - 1) / span;
-        m.rows = plan->grows[g];
-        nst[g] = (d.nr + m.rows - 1) / m.rows;
-        m.tile_base = slots;
-        m.ntiles = ntt[g] * nst[g];
-        slots += m.ntiles;
-        poff += round_up((int64_t)d.nr * m.ld, 64);
+        gin[g] = tiling::GatherIn{d.nr, d.nt, d.dx, d.dt, d.offset, plan->grows[g]};
     }
+    const tiling::Layout L = tiling::plan_layout(gin, span, plan->params.alpha1, plan->params.delta);
+    const std::vector<GatherMeta>& meta = L.meta;
+    const int32_t slots = L.slots;
+    const int64_t poff = L.padded_len;
     plan->h_meta = meta;
-    plan->h_ntt = ntt;
-    plan->h_nst = nst;
+    plan->h_ntt = L.ntt;
+    plan->h_nst = L.nst;
     const std::vector<Tile> tiles = layout_tiles(plan, std::vector<char>(plan->ngather, 1));
     if (tiles.size() > (size_t)INT32_MAX / 8) return fail(EMD_ERR_INVALID_ARGUMENT, "too many tiles");
     const bool realloc_tiles = (int32_t)tiles.size() != plan->ntiles || slots != plan->nslots || !plan->d_tiles;
@@ -393,21 +322,10 @@ emd_status build_chains(emd_plan* plan, const std::vector<char>& sel, const Swee
                         Chains<T>& ch, hipStream_t stream)
 {
     std::memset(&ch, 0, sizeof(ch));  // the graph key compares these bytes
-    std::vector<int> order;
-    for (int g = 0; g < plan->ngather; ++g)
-        if (sel[g]) order.push_back(g);
-    auto cells = [&](int g) { return (int64_t)plan->desc[g].nr * plan->desc[g].nt; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells(x) > cells(y); });
-    const int nc = std::max(1, std::min((int)order.size(), kChains));
-    std::vector<std::vector<char>> part(nc, std::vector<char>(plan->ngather, 0));
-    int64_t load[kChains] = {};
-    for (int g : order) {
-        int k = 0;
-        for (int j = 1; j < nc; ++j)
-            if (load[j] < load[k]) k = j;
-        part[k][g] = 1;
-        load[k] += cells(g);
-    }
+    std::vector<int64_t> cells(plan->ngather);
+    for (int g = 0; g < plan->ngather; ++g) cells[g] = (int64_t)plan->desc[g].nr * plan->desc[g].nt;
+    const std::vector<std::vector<char>> part = tiling::split_chains(cells, sel, kChains);
+    const int nc = (int)part.size();
     std::vector<std::vector<Tile>> tabs(nc);
     for (int k = 0; k < nc; ++k) {
         tabs[k] = layout_tiles(plan, part[k]);
@@ -610,7 +528,7 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
                 else ++out;
             }
             known_out = out;
-            if (live > 0 && live * 16 <= table_cells * 15) {
+            if (tiling::narrow_now(live, table_cells)) {
                 cst = build_chains<T>(plan, sel, sa, ch, stream);
                 if (cst != EMD_SUCCESS) return cst;
                 table_cells = live;

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "emd_tiling.h"  // OUT_LANES, GatherMeta, Tile
+
 namespace emd {
 
 // Per-gather status codes (same values as EMD_GATHER_* in the public header).
@@ -41,30 +43,6 @@ constexpr int NPART = 8;
 constexpr int NL1 = 6;
 constexpr int NPART_L1 = 16;
 constexpr int WAVE = 64;
-// A sweep wave owns OUT_LANES * V consecutive time samples in lanes 1..OUT_LANES;
-// lanes 0 and OUT_LANES + 1 carry the time-axis halo, the remaining lanes idle.
-// 56 lanes x 16 bytes = 896 bytes = 7 whole 128-byte cache lines, so the stores of
-// a row never leave a partially written line behind (a partial line costs a fill
-// read and a whole-line write-back).
-constexpr int OUT_LANES = 56;
-constexpr int HALO_LANE_R = OUT_LANES + 1;
-
-struct GatherMeta {
-    int32_t nr, nt, ld, ntiles;  // grid, padded pitch, sweep tiles of the gather
-    int32_t tile_base;           // first partial-sum slot (tiles own consecutive slots)
-    int32_t rows;                // receiver rows per tile (one strip)
-    int64_t poff;                // element offset in the padded workspace fields
-    int64_t uoff;                // element offset in the caller's batch buffers
-    double dx, dt;               // EMD grid spacings
-    double cm;                   // cell measure (dx if nr > 1, times dt if nt > 1)
-    double alpha1;               // initial step (delta lambda)^(-1/2) or user's
-};
-
-struct Tile {
-    int32_t g;      // gather (-1: empty padding entry)
-    int32_t r0, c0; // first output row, first output sample
-    int32_t slot;   // partial-sum slot (a gather's slots are contiguous)
-};
 
 // Per-gather scalar state, double-buffered by sweep parity.
 struct GState {

@@ -133,3 +133,20 @@ def test_library_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-3000:])
     assert "passed" in r.stdout
     assert _mapped(r.stderr, "libemd_mi355x_san.so") and _mapped(r.stderr, "libclang_rt.asan")
+
+
+def test_tile_bookkeeping_under_sanitizers(tmp_path):
+    # the host-only part of the solve's bookkeeping (csrc/emd_tiling.h: padded layout,
+    # tile tables over the XCDs, chains, narrowing rule) on 300 random batches, built
+    # with g++ and both sanitizers; every rule the sweep relies on is checked
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "host_tiling_check")
+    subprocess.check_call([gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           "-I", os.path.join(ROOT, "paper_1808_07284_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "host_tiling_check.cpp"), "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, env={**os.environ, **SAN_ENV}, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("ok: 300 batches")
