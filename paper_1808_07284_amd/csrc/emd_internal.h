@@ -81,15 +81,56 @@ struct SolveScalars {
 
 // ---------------------------------------------------------------- reductions
 
-// Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the same
-// value: at each level lanes l and l^m add the same two operands (IEEE addition
-// is commutative), so the result is bitwise identical on all lanes and all waves
-// that reduce the same data.
+// Data-parallel primitives (DPP): operand modifiers of the vector ALU that read
+// another lane of the wavefront, instead of a permute through the LDS.
+//   wave_shr:1  (dpp_ctrl 0x138): lane i reads lane i - 1; lane 0 reads 0
+//   wave_shl:1  (dpp_ctrl 0x130): lane i reads lane i + 1; lane 63 reads 0
+//   row_shr:n   (0x110 + n): lane i reads lane i - n of its row of 16; 0 before it
+//   row_bcast:15 / :31 (0x142 / 0x143): rows 1 and 3 read lane 15 of the row before
+//     them / rows 2 and 3 read lane 31 (the other rows keep the `old` operand, 0)
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, BOUND);
+}
+
+template <int CTRL, int ROW_MASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(dpp_i<CTRL, ROW_MASK, BOUND>(__float_as_int(v)));
+}
+
+template <int CTRL, int ROW_MASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ double dpp(double v)
+{
+    const int lo = dpp_i<CTRL, ROW_MASK, BOUND>(__double2loint(v));
+    const int hi = dpp_i<CTRL, ROW_MASK, BOUND>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// The value of the previous / next lane (the neighbouring time samples of the
+// sweep's lanes); the first / last lane of the wave receives 0.
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v) { return dpp<0x138>(v); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T v) { return dpp<0x130>(v); }
+
+// Sum over the 64 lanes of a wavefront, in a fixed order: inclusive prefix sums
+// inside each row of 16 lanes (row_shr 1, 2, 4, 8), the row totals carried across
+// rows (row_bcast 15, then 31), and lane 63's total moved to scalar registers, so
+// every lane (and every wave that reduces the same data) gets the same bits.  All 64
+// lanes must be active.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    v += dpp<0x111>(v);
+    v += dpp<0x112>(v);
+    v += dpp<0x114>(v);
+    v += dpp<0x118>(v);
+    v += dpp<0x142, 0xA, false>(v);
+    v += dpp<0x143, 0xC, false>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum n records of NP doubles (record p at src[p * NP]) in a fixed order: lane l

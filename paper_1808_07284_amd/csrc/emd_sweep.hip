@@ -481,15 +481,15 @@ struct Pipe {
     {
         constexpr int Q = P ^ 1;
         T b[V];
-        const T dt_next = __shfl_down(DT[P][0], 1, WAVE);
+        const T dt_next = lane_next(DT[P][0]);
         T zero_add[V];
         zero(zero_add);
         div_row<T, EDGE>(c, has_next, im > 0, DX[P], DXf, DT[P], dt_next, zero_add, b);
         T a[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) a[k] = AN[P][k] + b[k];
-        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
-        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        const T a_prev = lane_prev(a[V - 1]);
+        const T b_prev = lane_prev(b[V - 1]);
         if (im >= c.r0 && im < c.rend && c.lane_out) {
             const bool xg = im > 0;
 #pragma unroll
@@ -541,7 +541,7 @@ struct Pipe {
 
         // (1) residual of the current flux: A_n = div u_n + s on row i
         div_row<T, EDGE>(c, i + 1 < c.nr, has_prev, UX[X0], UX[X1], UT[P],
-                         __shfl_down(UT[P][0], 1, WAVE), SV[P], AN[P]);
+                         lane_next(UT[P][0]), SV[P], AN[P]);
         // (2) dual step: phi_n = phi_{n-1} + beta (A_n + theta (A_n - R))
 #pragma unroll
         for (int k = 0; k < V; ++k)
@@ -559,7 +559,7 @@ struct Pipe {
         }
         if constexpr (PROX) {
             // (3) primal update with the backward-difference gradient of phi_n
-            const T ph_prev = __shfl_up(PHN[P][V - 1], 1, WAVE);
+            const T ph_prev = lane_prev(PHN[P][V - 1]);
             const T wgx = has_prev ? c.idx : T(0);
             T u1x[V], u1t[V];
             T l1 = T(0), l2 = T(0);
@@ -720,15 +720,15 @@ struct PipeUp {
     {
         constexpr int Q = P ^ 1;
         T b[V];
-        const T dt_next = __shfl_down(DT[P][0], 1, WAVE);
+        const T dt_next = lane_next(DT[P][0]);
         T zero_add[V];
         zero(zero_add);
         div_row<T, EDGE>(c, im + 1 < c.nr, im > 0, DX[P], DX[Q], DT[P], dt_next, zero_add, b);
         T a[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) a[k] = AN[Q][k] + b[k];
-        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
-        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        const T a_prev = lane_prev(a[V - 1]);
+        const T b_prev = lane_prev(b[V - 1]);
         const bool own = im >= c.r0 && im < c.rend;
         const bool own_below = im + 1 >= c.r0 && im + 1 < c.rend;
         if ((own || own_below) && c.lane_out) {
@@ -774,7 +774,7 @@ struct PipeUp {
 
         // (1) residual of the current flux: A_n = div u_n + s on row i
         div_row<T, EDGE>(c, i + 1 < c.nr, i > 0, UX[X0], UX[X3], UT[X0],
-                         __shfl_down(UT[X0][0], 1, WAVE), SV[P], AN[P]);
+                         lane_next(UT[X0][0]), SV[P], AN[P]);
         // (2) dual step on row i
 #pragma unroll
         for (int k = 0; k < V; ++k)
@@ -793,7 +793,7 @@ struct PipeUp {
             const int in = i + 1;
             const bool own_n = (in >= c.r0) && (in < c.rend);
             const uint32_t so_n = c.vb_st + (own_n ? (uint32_t)in * c.row_bytes : OOB);
-            const T ph_prev = __shfl_up(PHN[Q][V - 1], 1, WAVE);
+            const T ph_prev = lane_prev(PHN[Q][V - 1]);
             const T wgx = in > 0 ? c.idx : T(0);
             T u1x[V], u1t[V];
             T l1 = T(0), l2 = T(0);
@@ -881,18 +881,18 @@ __device__ void eval_tile(const TileCtx<T>& c, double (&acc)[NPART_L1])
         bload(c.uxo, o1, ox1);
         bload(c.si, o0, sv);
         T an[V], dx0[V], dx1[V], dt0[V], b[V], a[V];
-        div_row<T, true>(c, im + 1 < c.nr, im > 0, ox0, ox1, ot0, __shfl_down(ot0[0], 1, WAVE), sv, an);
+        div_row<T, true>(c, im + 1 < c.nr, im > 0, ox0, ox1, ot0, lane_next(ot0[0]), sv, an);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             dx0[k] = nx0[k] - ox0[k];
             dx1[k] = nx1[k] - ox1[k];
             dt0[k] = nt0[k] - ot0[k];
         }
-        div_row<T, true>(c, im + 1 < c.nr, im > 0, dx0, dx1, dt0, __shfl_down(dt0[0], 1, WAVE), zero_add, b);
+        div_row<T, true>(c, im + 1 < c.nr, im > 0, dx0, dx1, dt0, lane_next(dt0[0]), zero_add, b);
 #pragma unroll
         for (int k = 0; k < V; ++k) a[k] = an[k] + b[k];
-        const T a_prev = __shfl_up(a[V - 1], 1, WAVE);
-        const T b_prev = __shfl_up(b[V - 1], 1, WAVE);
+        const T a_prev = lane_prev(a[V - 1]);
+        const T b_prev = lane_prev(b[V - 1]);
         if (im >= c.r0 && c.lane_out) {
             const bool xg = im > 0;
             T l1 = T(0), l2 = T(0);
@@ -1220,7 +1220,7 @@ struct Pipe2 {
     __device__ __forceinline__ void prox_row(const T (&ux)[V], const T (&ut)[V], const T (&ph)[V],
                                              const T (&pu)[V], bool has_prev, T (&ox)[V], T (&ot)[V]) const
     {
-        const T ph_prev = __shfl_up(ph[V - 1], 1, WAVE);
+        const T ph_prev = lane_prev(ph[V - 1]);
         const T wgx = has_prev ? c.idx : T(0);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -1286,8 +1286,8 @@ struct Pipe2 {
         const int m = i - 1;
         const bool nxt = i < c.nr, prv = m > 0;
         T a0[V], a1[V];
-        div_row<T, EDGE>(c, nxt, prv, LX[PV], LX[C], LT[PV], __shfl_down(LT[PV][0], 1, WAVE), LS[PV], a0);
-        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], __shfl_down(P1T[Q][0], 1, WAVE), LS[PV], a1);
+        div_row<T, EDGE>(c, nxt, prv, LX[PV], LX[C], LT[PV], lane_next(LT[PV][0]), LS[PV], a0);
+        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], lane_next(P1T[Q][0]), LS[PV], a1);
         dual_row(a1, a0, LP[PV], D1[Q]);
         if constexpr (!TWO) {
             // one iteration: u_{k+1} of row i - 1 and phi_{k+1} of row i - 1 are the outputs
@@ -1309,7 +1309,7 @@ struct Pipe2 {
             // A_{k+2} and D2 of row i - 2
             const int m2 = i - 2;
             T a2[V], d2[V];
-            div_row<T, EDGE>(c, i - 1 < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], __shfl_down(P2T[P][0], 1, WAVE),
+            div_row<T, EDGE>(c, i - 1 < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], lane_next(P2T[P][0]),
                              LS[PV2], a2);
             dual_row(a2, A1[P], D1[P], d2);
             store(c.phio, store_off(m2), d2);
