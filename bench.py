@@ -2,11 +2,17 @@
 """Benchmark of the EMD misfit hot path on one MI355X.
 
 A step is the whole path over one batch of synthetic gathers already resident in
-HBM: emd_decompose -> emd_pdhg_solve (PDHG with linesearch, every gather run to
-the relative-residual stop rule) -> emd_adjoint_source.  The metric is PDHG
-cell-updates per second (sum over gathers of nr * nt * iterations, divided by the
-step time) for the batched FP32 solve; the plain FP64 solve of the same batch, one
-gather per launch sequence, is timed beside it, and their EMDs are compared.
+HBM: emd_decompose -> the PDHG-with-linesearch solve, started coarse-to-fine (the
+multi-grid strategy the paper applies to the EMD: the data restricted to coarser
+grids are solved first, and each solution, interpolated, starts the next finer
+solve; every level runs to the relative-residual stop rule) -> emd_adjoint_source.
+The metric is PDHG cell-updates per second over all levels (sum of nr * nt *
+iterations, divided by the step time) for the batched FP32 solve; the EMD of the
+first gathers is checked against FP64 solves of them taken far past the stop rule
+(the accuracy the metric is quoted at), and the plain FP64 solve of the same gathers,
+one gather per plan, is timed beside it.  Further legs: the solve without the
+coarse start, plain fixed-step PDHG with two iterations per sweep, the 16 x 4000 x
+1600 batch at a fixed budget, the one-pass kernels, and the CPU oracle.
 
 Default workload: 64 gathers, nt ~ U{1500..3000}, nr ~ U{200..500}, 4-8 hyperbolic
 events (seed 3).  Prints one JSON line.
@@ -29,14 +35,16 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi, R
 # Bytes crossing the L2 boundary per sweep over the algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
-# sweep source with this digest; the traffic figure is null for any other source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "22f0d84a0f0a921e", "ratio": 1.072}
+# sweep source with this digest, per kernel; the traffic figure is null for any other
+# source.
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "0fd4afb31702c329",
+                    "ratio": {"k_sweep<float, false>": 1.0727, "k_sweep2<float>": 1.1618}}
 
 
 def sweep_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("emd_sweep.hip", "emd_internal.h", "emd_abi.hip"):
+    for f in ("emd_sweep.hip", "emd_internal.h", "emd_abi.hip", "emd_tiling.h"):
         with open(os.path.join(ROOT, "paper_1808_07284_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -59,12 +67,33 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_step(E, plan, pcal, pobs, bufs):
-    s, mass = E.emd_decompose(plan, pcal, pobs, s_out=bufs["s"], mass_out=bufs["mass"])
-    emd, phi, _, info = E.emd_pdhg_solve(plan, s, phi=bufs["phi"], mass=mass,
-                                         emd_out=bufs["emd"], info_out=bufs["info"])
+def run_step(E, plan, pcal, pobs, bufs, mg=None):
+    """decompose -> solve (coarse-to-fine when mg is given) -> adjoint source."""
+    if mg is None:
+        s, mass = E.emd_decompose(plan, pcal, pobs, s_out=bufs["s"], mass_out=bufs["mass"])
+        emd, phi, _, info = E.emd_pdhg_solve(plan, s, phi=bufs["phi"], mass=mass,
+                                             emd_out=bufs["emd"], info_out=bufs["info"])
+    else:
+        emd, phi, _, info, mass = mg.solve(pcal, pobs, emd_out=bufs["emd"], info_out=bufs["info"])
     E.emd_adjoint_source(plan, phi, pcal, pobs, mass, psi_out=bufs["psi"])
     return emd, info
+
+
+def step_stats(plan, mg=None):
+    """Cell updates, sweep time (HIP events the library records) and sweeps of the
+    last step, over the fine plan and its coarse levels."""
+    plans = [plan] + ([lv[0] for lv in mg.levels] if mg is not None else [])
+    qs = [p.query() for p in plans]
+    return (sum(q["last_cell_updates"] for q in qs), sum(q["last_sweep_ms"] for q in qs),
+            sum(q["last_sweeps"] for q in qs))
+
+
+def parse_levels(spec, workload_name):
+    if spec == "auto":
+        spec = "1x4,2x4" if workload_name == "c5" else "1x2,1x2"
+    if spec == "none":
+        return []
+    return [tuple(int(v) for v in f.split("x")) for f in spec.split(",")]
 
 
 def fp64_reference(E, torch, pcal, pobs, desc, idx, tol, leg):
@@ -160,10 +189,12 @@ def main():
     ap.add_argument("--f64-gathers", type=int, default=4,
                     help="gathers of the workload solved by the plain FP64 path (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--multigrid", default="auto", metavar="FRxFT[,FRxFT...]",
-                    help="also time the coarse-to-fine solve with these level factors ('none': skip; "
-                         "'auto': the measured best for the workload, 1x4,2x4 for c5, else 1x2)")
-    ap.add_argument("--mg-steps", type=int, default=1, help="timed coarse-to-fine steps")
+    ap.add_argument("--coarse", default="auto", metavar="FRxFT[,FRxFT...]",
+                    help="coarse levels that start the timed solve, finest first, each grouping FR "
+                         "receivers by FT samples of the level above ('none': a plain solve; 'auto': "
+                         "1x4,2x4 for c5, else 1x2,1x2)")
+    ap.add_argument("--fine-only-steps", type=int, default=1,
+                    help="timed steps of the same solve without the coarse start (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--gate-gathers", type=int, default=4,
                     help="gathers whose FP32 EMD is checked against an FP64 reference (0: skip)")
@@ -229,6 +260,8 @@ def main():
             "mass": torch.empty(len(gathers), 3, dtype=torch.float64, device=dev),
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
             "info": torch.empty(len(gathers) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
+    levels = parse_levels(args.coarse, args.workload)
+    mg = E.Multigrid(plan, levels) if levels else None
 
     # Accuracy gate (untimed): the FP32 EMD of the first gathers at the stop rule
     # against FP64 solves of them taken far past it.  If the gate fails, the stop rule
@@ -252,7 +285,7 @@ def main():
         return float(err.max()), float(perr.max()), err
 
     for w in range(max(args.warmup, 1 if gate is not None else 0)):
-        emd_w, info_w = run_step(E, plan, pcal, pobs, bufs)
+        emd_w, info_w = run_step(E, plan, pcal, pobs, bufs, mg)
         torch.cuda.synchronize()
         log(f"warmup {w} done")
     tightened = []
@@ -266,7 +299,7 @@ def main():
             tightened.append({"tol_res": params.tol_res, "emd_rel_err_max": err})
             params = dataclasses.replace(params, tol_res=params.tol_res * 0.3)
             plan.set_params(params)
-            emd_w, info_w = run_step(E, plan, pcal, pobs, bufs)
+            emd_w, info_w = run_step(E, plan, pcal, pobs, bufs, mg)
             torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
@@ -279,12 +312,12 @@ def main():
     e0.record(stream)
     t0 = time.perf_counter()
     for k in range(args.steps):
-        emd, info = run_step(E, plan, pcal, pobs, bufs)
-        q = plan.query()
-        cell_updates += q["last_cell_updates"]
-        sweep_ms += q["last_sweep_ms"]
-        sweeps += q["last_sweeps"]
-        log(f"step {k}: {q['last_sweeps']} sweeps, {q['last_sweep_ms']:.1f} ms in sweeps")
+        emd, info = run_step(E, plan, pcal, pobs, bufs, mg)
+        cu_k, ms_k, sw_k = step_stats(plan, mg)
+        cell_updates += cu_k
+        sweep_ms += ms_k
+        sweeps += sw_k
+        log(f"step {k}: {sw_k} sweeps, {ms_k:.1f} ms in sweeps")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -309,8 +342,9 @@ def main():
     algo_bytes = BYTES_PER_CELL_ITER["f32"] * cell_updates
     achieved = algo_bytes / (sweep_ms / 1e3) / 1e9 if sweep_ms > 0 else 0.0
     traffic = None
-    if args.ls == "l2" and sweep_source_digest() == MEASURED_TRAFFIC["sweep_source_sha256_16"]:
-        traffic = round(MEASURED_TRAFFIC["ratio"] * achieved, 1)
+    measured = sweep_source_digest() == MEASURED_TRAFFIC["sweep_source_sha256_16"]
+    if args.ls == "l2" and measured:
+        traffic = round(MEASURED_TRAFFIC["ratio"]["k_sweep<float, false>"] * achieved, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_sweep<float, {'true' if args.ls == 'l1' else 'false'}>", "launches": int(sweeps),
@@ -365,21 +399,26 @@ def main():
         for j, k in enumerate(sample):
             nr, nt, dx, dt, off = desc[k]
             pl = E.Plan([(nr, nt, dx, dt, 0)], nr * nt, p64)
+            mg64 = E.Multigrid(pl, levels) if levels else None
             a = pc64[off:off + nr * nt]
             b = po64[off:off + nr * nt]
+            b64 = {"s": pl.empty(), "phi": pl.empty(), "psi": pl.empty(),
+                   "mass": torch.empty(1, 3, dtype=torch.float64, device=dev),
+                   "emd": torch.empty(1, dtype=torch.float64, device=dev),
+                   "info": torch.empty(E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
             torch.cuda.synchronize()
             t64 = time.perf_counter()
-            s, mass = E.emd_decompose(pl, a, b)
-            e, phi, _, inf64 = E.emd_pdhg_solve(pl, s, mass=mass)
-            E.emd_adjoint_source(pl, phi, a, b, mass)
+            e, _ = run_step(E, pl, a, b, b64, mg64)
             torch.cuda.synchronize()
             el64 += time.perf_counter() - t64
-            cu64 += pl.query()["last_cell_updates"]
+            cu64 += step_stats(pl, mg64)[0]
             emd64[j] = float(e.cpu()[0])
+            if mg64 is not None:
+                mg64.close()
             pl.close()
         rel = np.abs(emd32[sample] - emd64) / np.abs(emd64)
-        extra["plain_f64"] = {"what": "the same fused sweep in FP64, one gather per plan and launch "
-                                      "sequence, on the first gathers of the workload",
+        extra["plain_f64"] = {"what": "the same solve (coarse start, fused sweep) in FP64, one gather per "
+                                      "plan and launch sequence, on the first gathers of the workload",
                               "value": cu64 / el64, "unit": "cell-updates/s", "seconds": round(el64, 2),
                               "gathers": len(sample), "stop_rule": f"{params.tol_res:g}",
                               "speedup_f32_batched": round(value / (cu64 / el64), 2),
@@ -405,16 +444,17 @@ def main():
         planf = E.Plan(desc, len(pcal_h), pf)
         if rows:
             planf.set_gather_tiling(rows)
-        run_step(E, planf, pcal, pobs, bufs)  # captures the graph
+        mgf = E.Multigrid(planf, levels) if levels else None
+        run_step(E, planf, pcal, pobs, bufs, mgf)  # captures the graphs
         torch.cuda.synchronize()
         cuf, msf, swf = 0, 0.0, 0
         e0.record(stream)
         for _ in range(args.fixed_steps):
-            emd_f, info_f = run_step(E, planf, pcal, pobs, bufs)
-            qf = planf.query()
-            cuf += qf["last_cell_updates"]
-            msf += qf["last_sweep_ms"]
-            swf += qf["last_sweeps"]
+            emd_f, info_f = run_step(E, planf, pcal, pobs, bufs, mgf)
+            cu_k, ms_k, sw_k = step_stats(planf, mgf)
+            cuf += cu_k
+            msf += ms_k
+            swf += sw_k
         e1.record(stream)
         torch.cuda.synchronize()
         stepf = e0.elapsed_time(e1) / args.fixed_steps
@@ -422,13 +462,15 @@ def main():
         # algorithmic bytes: 28 per cell per sweep of two iterations (14 per iteration)
         achf = 14 * cuf / (msf / 1e3) / 1e9
         extra["plain_pdhg_two_iterations_per_sweep"] = {
-            "what": "plain PDHG with fixed steps, two iterations per HBM pass, FP32, same stop rule",
+            "what": "plain PDHG with fixed steps, two iterations per HBM pass, FP32, same coarse start "
+                    "and stop rule",
             "value": cuf / args.fixed_steps / (stepf / 1e3), "unit": "cell-updates/s",
             "ms_per_step": round(stepf, 3), "speedup_vs_linesearch_step": round(ms_per_step / stepf, 3),
             "iters_mean": float(inff["iters"].mean()), "iters_max": int(inff["iters"].max()),
             "statuses": np.bincount(inff["status"], minlength=7).tolist(),
             "roofline": {"bound": "hbm", "achieved": round(achf, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achf / HBM_PEAK_GBS, 4), "kernel": "k_sweep2<float>",
+                         "traffic": round(MEASURED_TRAFFIC["ratio"]["k_sweep2<float>"] * achf, 1) if measured else None,
                          "launches": int(swf), "avg_launch_us": round(msf * 1e3 / max(swf, 1), 2),
                          "algo_bytes_per_launch": int(14 * cuf / max(swf, 1))}}
         if ref is not None:
@@ -437,6 +479,8 @@ def main():
                 np.max(np.abs(ef / ref - 1)))
         log(f"fixed steps, two iterations per sweep: {stepf:.1f} ms/step ({ms_per_step / stepf:.2f}x the "
             f"linesearch), iters mean {inff['iters'].mean():.0f}, sweeps at {achf:.0f} GB/s")
+        if mgf is not None:
+            mgf.close()
         planf.close()
 
     if args.c5_iters > 0 and args.workload != "c5":
@@ -481,42 +525,35 @@ def main():
         plan5.close()
         del pc5, po5, b5
 
-    if args.multigrid == "auto":
-        args.multigrid = "1x4,2x4" if args.workload == "c5" else "1x2"
-    if args.multigrid != "none" and args.mg_steps > 0:
-        # the same step (decompose, solve, adjoint source) with the solve started from
-        # coarser grids; the headline metric stays the plain solve's
-        factors = [tuple(int(v) for v in f.split("x")) for f in args.multigrid.split(",")]
-        mg = E.Multigrid(plan, factors)
-
-        def mg_step():
-            emd_m, phi_m, _, info_m, mass_m = mg.solve(pcal, pobs)
-            E.emd_adjoint_source(plan, phi_m, pcal, pobs, mass_m, psi_out=bufs["psi"])
-            return emd_m, info_m
-
-        mg_step()  # the coarse plans' first solves capture their graphs
+    if args.fine_only_steps > 0 and mg is not None:
+        # the same step with the solve started cold on the fine grid: the residual rule
+        # certifies feasibility, not optimality, and without the coarse start a few
+        # gathers stop feasible but above the optimum (see the accuracy notes)
+        run_step(E, plan, pcal, pobs, bufs)
         torch.cuda.synchronize()
+        cuo, mso = 0, 0.0
         e0.record(stream)
-        for _ in range(args.mg_steps):
-            emd_m, info_m = mg_step()
+        for _ in range(args.fine_only_steps):
+            emd_o, info_o = run_step(E, plan, pcal, pobs, bufs)
+            cu_k, ms_k, _ = step_stats(plan)
+            cuo += cu_k
+            mso += ms_k
         e1.record(stream)
         torch.cuda.synchronize()
-        mg_ms = e0.elapsed_time(e1) / args.mg_steps
-        im = E.info_numpy(info_m)
-        rel_m = np.abs(emd_m.cpu().numpy() / emd32 - 1)
-        extra["multigrid"] = {
-            "factors": args.multigrid, "ms_per_step": round(mg_ms, 3),
-            "plain_ms_per_step": round(ms_per_step, 3), "speedup": round(ms_per_step / mg_ms, 3),
-            "statuses": np.bincount(im["status"], minlength=7).tolist(),
-            "fine_iters_mean": float(im["iters"].mean()), "fine_iters_max": int(im["iters"].max()),
-            "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mg.last_info],
-            "emd_rel_diff_vs_plain_max": float(rel_m.max())}
+        stepo = e0.elapsed_time(e1) / args.fine_only_steps
+        io = E.info_numpy(info_o)
+        rel_o = np.abs(emd_o.cpu().numpy() / emd32 - 1)
+        extra["fine_only_start"] = {
+            "what": "the same solve started cold on the fine grid", "ms_per_step": round(stepo, 3),
+            "value": cuo / args.fine_only_steps / (stepo / 1e3), "unit": "cell-updates/s",
+            "coarse_start_speedup": round(stepo / ms_per_step, 3),
+            "iters_mean": float(io["iters"].mean()), "iters_max": int(io["iters"].max()),
+            "emd_rel_diff_vs_coarse_start_max": float(rel_o.max())}
         if ref is not None:
-            extra["multigrid"]["emd_rel_err_vs_ref_max"] = float(
-                np.max(np.abs(emd_m.cpu().numpy()[:len(ref)] / ref - 1)))
-        log(f"coarse-to-fine {args.multigrid}: {mg_ms:.1f} ms/step ({ms_per_step / mg_ms:.2f}x), "
-            f"fine iters mean {im['iters'].mean():.0f}, EMD rel diff vs plain max {rel_m.max():.2e}")
-        mg.close()
+            extra["fine_only_start"]["emd_rel_err_vs_ref_max"] = float(
+                np.max(np.abs(emd_o.cpu().numpy()[:len(ref)] / ref - 1)))
+        log(f"cold fine start: {stepo:.1f} ms/step (the coarse start is {stepo / ms_per_step:.2f}x faster), "
+            f"iters mean {io['iters'].mean():.0f}, EMD rel diff vs coarse start max {rel_o.max():.2e}")
 
     out = {"metric": "PDHG cell-updates/s to 1e-5 rel EMD err, batched FP32 vs plain FP64; % HBM peak",
            "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -525,7 +562,10 @@ def main():
            "config": {"workload": wdesc, "gathers": len(gathers), "cells": cells,
                       "stop_rule": f"||div u + s||/||s|| <= {params.tol_res:g}", "max_iter": args.max_iter,
                       "linesearch": args.ls,
-                      "iters_mean": float(inf["iters"].mean()), "iters_max": int(inf["iters"].max()),
+                      "coarse_levels": ",".join(f"{a}x{b}" for a, b in levels) or "none",
+                      "fine_iters_mean": float(inf["iters"].mean()), "fine_iters_max": int(inf["iters"].max()),
+                      "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mg.last_info]
+                      if mg is not None else [],
                       "tile_rows": heights if heights else (args.rows or plan.query()["rows_per_tile"]),
                       "tile_rows_per_gather": plan.gather_tiling()},
            "roofline": roofline, "cpu_baseline": cpu}
@@ -534,6 +574,8 @@ def main():
         out["accuracy_gate"] = gate
     out.update(extra)
     print(json.dumps(out))
+    if mg is not None:
+        mg.close()
     plan.close()
 
 
