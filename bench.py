@@ -5,7 +5,8 @@ A step is the whole path over one batch of synthetic gathers already resident in
 HBM: emd_decompose -> the PDHG-with-linesearch solve, started coarse-to-fine (the
 multi-grid strategy the paper applies to the EMD: the data restricted to coarser
 grids are solved first, and each solution, interpolated, starts the next finer
-solve; every level runs to the relative-residual stop rule) -> emd_adjoint_source.
+solve; every level runs to a relative-residual stop rule, the coarse ones to 1.5
+times the fine one's) -> emd_adjoint_source.
 The metric is PDHG cell-updates per second over all levels (sum of nr * nt *
 iterations, divided by the step time) for the batched FP32 solve; the EMD of the
 first gathers is checked against FP64 solves of them taken far past the stop rule
@@ -90,7 +91,7 @@ def step_stats(plan, mg=None):
 
 def parse_levels(spec, workload_name):
     if spec == "auto":
-        spec = "1x4,2x4" if workload_name == "c5" else "1x2,1x2"
+        spec = "1x4,2x4" if workload_name == "c5" else "1x2,1x2,1x2"
     if spec == "none":
         return []
     return [tuple(int(v) for v in f.split("x")) for f in spec.split(",")]
@@ -192,7 +193,9 @@ def main():
     ap.add_argument("--coarse", default="auto", metavar="FRxFT[,FRxFT...]",
                     help="coarse levels that start the timed solve, finest first, each grouping FR "
                          "receivers by FT samples of the level above ('none': a plain solve; 'auto': "
-                         "1x4,2x4 for c5, else 1x2,1x2)")
+                         "1x4,2x4 for c5, else 1x2,1x2,1x2)")
+    ap.add_argument("--coarse-tol-factor", type=float, default=1.5,
+                    help="stop rule of the coarse levels over the fine one's")
     ap.add_argument("--fine-only-steps", type=int, default=1,
                     help="timed steps of the same solve without the coarse start (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60)
@@ -261,7 +264,7 @@ def main():
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
             "info": torch.empty(len(gathers) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
     levels = parse_levels(args.coarse, args.workload)
-    mg = E.Multigrid(plan, levels) if levels else None
+    mg = E.Multigrid(plan, levels, coarse_tol_factor=args.coarse_tol_factor) if levels else None
 
     # Accuracy gate (untimed): the FP32 EMD of the first gathers at the stop rule
     # against FP64 solves of them taken far past it.  If the gate fails, the stop rule
@@ -399,7 +402,7 @@ def main():
         for j, k in enumerate(sample):
             nr, nt, dx, dt, off = desc[k]
             pl = E.Plan([(nr, nt, dx, dt, 0)], nr * nt, p64)
-            mg64 = E.Multigrid(pl, levels) if levels else None
+            mg64 = E.Multigrid(pl, levels, coarse_tol_factor=args.coarse_tol_factor) if levels else None
             a = pc64[off:off + nr * nt]
             b = po64[off:off + nr * nt]
             b64 = {"s": pl.empty(), "phi": pl.empty(), "psi": pl.empty(),
@@ -444,7 +447,7 @@ def main():
         planf = E.Plan(desc, len(pcal_h), pf)
         if rows:
             planf.set_gather_tiling(rows)
-        mgf = E.Multigrid(planf, levels) if levels else None
+        mgf = E.Multigrid(planf, levels, coarse_tol_factor=args.coarse_tol_factor) if levels else None
         run_step(E, planf, pcal, pobs, bufs, mgf)  # captures the graphs
         torch.cuda.synchronize()
         cuf, msf, swf = 0, 0.0, 0
@@ -563,6 +566,7 @@ def main():
                       "stop_rule": f"||div u + s||/||s|| <= {params.tol_res:g}", "max_iter": args.max_iter,
                       "linesearch": args.ls,
                       "coarse_levels": ",".join(f"{a}x{b}" for a, b in levels) or "none",
+                      "coarse_stop_rule": f"{args.tol * args.coarse_tol_factor:g}" if levels else None,
                       "fine_iters_mean": float(inf["iters"].mean()), "fine_iters_max": int(inf["iters"].max()),
                       "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mg.last_info]
                       if mg is not None else [],

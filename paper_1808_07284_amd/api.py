@@ -441,18 +441,31 @@ class Multigrid:
     coarse plans are built once, with the fine plan's parameters unless given; a
     coarse level never uses mass mode `none` (block means over the ragged last
     blocks shift the two masses slightly, and a coarse level only supplies a start),
-    it balances the masses instead."""
+    it balances the masses instead.  `coarse_rows` is the tile height of the coarse
+    plans (None: the library's default): a coarse batch is a few times smaller than
+    the fine one, so more of its sweeps run with only its slowest gathers left, and
+    there a shorter tile gives more, shorter-lived waves.  `coarse_tol_factor`
+    scales the coarse levels' stop rule (tol_res) against the one of their
+    parameters: a coarse level only supplies a start, which the fine solve then
+    takes to its own rule."""
 
-    def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None):
+    def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None,
+                 coarse_rows: int | None = 8, coarse_tol_factor: float = 1.0):
         self.fine = plan
         self.levels = []  # (coarse plan, fr, ft), finest first
         prm = params or plan.params
         if prm.mass_mode == L.MASS_NONE:
             prm = dataclasses.replace(prm, mass_mode=L.MASS_BALANCE)
+        if not coarse_tol_factor > 0:
+            raise ValueError("coarse_tol_factor must be > 0")
+        prm = dataclasses.replace(prm, tol_res=prm.tol_res * float(coarse_tol_factor))
         descs = plan.descs
         for fr, ft in factors:
             cd, n = coarse_descs(descs, int(fr), int(ft))
-            self.levels.append((Plan(cd, n, prm, device=plan.device), int(fr), int(ft)))
+            cp = Plan(cd, n, prm, device=plan.device)
+            if coarse_rows:
+                cp.set_tiling(int(coarse_rows))
+            self.levels.append((cp, int(fr), int(ft)))
             descs = cd
         self.last_info = []  # per level, coarsest first: the solve info of the last start()
 
