@@ -173,6 +173,16 @@ std::vector<Tile> layout_tiles(const emd_plan* plan, const std::vector<char>& se
     return tiling::layout_tiles(L, OUT_LANES * plan->vec, sel);
 }
 
+// Device memory a plan owns: the nine padded field copies, the scalar state, the
+// partial-sum slots of both linesearch forms, the tile tables and the metadata.
+int64_t plan_workspace_bytes(const emd_plan* plan)
+{
+    return (int64_t)plan->elem * plan->padded_len * 9 + (int64_t)sizeof(GState) * 2 * plan->ngather +
+           (int64_t)sizeof(double) * (NPART + NPART_L1) * 2 * plan->nslots +
+           (int64_t)sizeof(Tile) * (1 + 2 * kChains) * plan->ntiles +
+           (int64_t)sizeof(GatherMeta) * plan->ngather;
+}
+
 emd_status build_tiles(emd_plan* plan)
 {
     const int span = OUT_LANES * plan->vec;
@@ -218,6 +228,7 @@ emd_status build_tiles(emd_plan* plan)
     HIP_TRY(hipMemset(plan->d_part, 0, sizeof(double) * NPART * 2 * slots));
     HIP_TRY(hipMemset(plan->d_part_l1, 0, sizeof(double) * NPART_L1 * 2 * slots));
     destroy_graph(plan);
+    plan->workspace_bytes = plan_workspace_bytes(plan);
     return EMD_SUCCESS;
 }
 
@@ -302,7 +313,8 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
 }
 
 // The sweep launches of a solve.  The running gathers are split into up to kChains
-// groups of about equal cells, each with its own tile table (laid out over the XCDs
+// groups of about equal cells (one group once they hold fewer than
+// tiling::kChainMinTiles tiles), each with its own tile table (laid out over the XCDs
 // like the full table), and a captured chunk runs the groups as independent chains
 // of launches: while the last waves of one group's sweep drain, the other group's
 // next sweep fills the GPU.  A gather belongs to exactly one chain, so its sweeps
@@ -324,7 +336,11 @@ emd_status build_chains(emd_plan* plan, const std::vector<char>& sel, const Swee
     std::memset(&ch, 0, sizeof(ch));  // the graph key compares these bytes
     std::vector<int64_t> cells(plan->ngather);
     for (int g = 0; g < plan->ngather; ++g) cells[g] = (int64_t)plan->desc[g].nr * plan->desc[g].nt;
-    const std::vector<std::vector<char>> part = tiling::split_chains(cells, sel, kChains);
+    int64_t sel_tiles = 0;
+    for (int g = 0; g < plan->ngather; ++g)
+        if (sel[g]) sel_tiles += plan->h_meta[g].ntiles;
+    const std::vector<std::vector<char>> part =
+        tiling::split_chains(cells, sel, tiling::chain_count(sel_tiles, kChains));
     const int nc = (int)part.size();
     std::vector<std::vector<Tile>> tabs(nc);
     for (int k = 0; k < nc; ++k) {
@@ -672,10 +688,6 @@ emd_status emd_plan_create(const emd_gather_desc* h_desc, int32_t ngather, int64
         cleanup(EMD_SUCCESS);
         return fail(EMD_ERR_HIP, "workspace initialisation failed");
     }
-    plan->workspace_bytes = (int64_t)fbytes + (int64_t)sizeof(GState) * 2 * ngather +
-                            (int64_t)sizeof(double) * (NPART + NPART_L1) * 2 * plan->nslots +
-                            (int64_t)sizeof(Tile) * (1 + 2 * kChains) * plan->ntiles +
-                            (int64_t)sizeof(GatherMeta) * ngather;
     *out = plan;
     return EMD_SUCCESS;
 }

@@ -177,6 +177,13 @@ inline std::vector<std::vector<char>> split_chains(const std::vector<int64_t>& c
     return part;
 }
 
+// Chains of launches for a table of `tiles` real tiles: up to max_chains once a launch
+// is long enough for one chain's draining waves to overlap the other's next sweep;
+// below kChainMinTiles a launch lasts about one wave's march whatever its size, two
+// such launches barely overlap, and one chain over all of them is faster.
+constexpr int64_t kChainMinTiles = 2048;
+inline int chain_count(int64_t tiles, int max_chains) { return tiles >= kChainMinTiles ? max_chains : 1; }
+
 // Finished gathers leave the sweep's tables once the running ones hold at most 15/16
 // of the cells the tables cover (tiles keep their shape and slots, so no result
 // changes; only the launch gets smaller).

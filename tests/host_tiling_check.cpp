@@ -135,6 +135,11 @@ int main()
             CHECK(*mm.second - *mm.first <= biggest);
         }
 
+        // the chain count: two chains from kChainMinTiles real tiles on
+        const int64_t nt_sel = want;
+        CHECK(tiling::chain_count(nt_sel, 2) == (nt_sel >= tiling::kChainMinTiles ? 2 : 1));
+        CHECK(tiling::chain_count(tiling::kChainMinTiles - 1, 2) == 1 && tiling::chain_count(tiling::kChainMinTiles, 2) == 2);
+
         // the narrowing rule
         const int64_t table = uni(1, 1 << 20);
         const int64_t live = uni(0, (int)table);

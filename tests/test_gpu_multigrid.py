@@ -228,3 +228,40 @@ def test_fwi_loop_multigrid_then_warm_start():
     log(f"  cold solve of the last model: {plan.query()['last_cell_updates']}")
     mg.close()
     plan.close()
+
+
+def test_multigrid_coarse_level_settings():
+    # the coarse plans' stop rule is the fine one's times coarse_tol_factor and their
+    # tiles are coarse_rows high; each level then stops at its own rule
+    gs = to_precision([config2_gather(nr=24, nt=400, f_peak=4.0, dtype=np.float64),
+                       config2_gather(seed=5, nr=16, nt=300, f_peak=4.0, dtype=np.float64)], np.float32)
+    p = E.SolverParams(precision=E.F32, tol_res=1e-5, max_iter=100000)
+    plan, pcal, pobs, desc = make_plan(gs, p)
+    with pytest.raises(ValueError):
+        E.Multigrid(plan, ((1, 2),), coarse_tol_factor=0.0)
+    plain = E.Multigrid(plan, ((1, 2),), coarse_rows=None)
+    q16 = plain.levels[0][0].query()
+    assert q16["rows_per_tile"] == 16
+    assert plain.levels[0][0].params.tol_res == p.tol_res
+    plain.close()
+    mg = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_tol_factor=1.5)
+    for cp, _, _ in mg.levels:
+        assert cp.params.tol_res == pytest.approx(1.5e-5, rel=1e-15)
+        assert cp.query()["rows_per_tile"] == 8
+    # the shorter tiles' extra partial-sum slots are accounted for (the table itself is
+    # padded to eight runs of whole blocks, so on gathers this small it keeps its length)
+    q8 = mg.levels[0][0].query()
+    assert q8["tiles"] >= q16["tiles"] and q8["workspace_bytes"] > q16["workspace_bytes"]
+    emd, _, _, info, _ = mg.solve(pcal, pobs)
+    torch.cuda.synchronize()
+    conv = E.GATHER_STATUS.index("CONVERGED")
+    for li in mg.last_info:
+        ci = E.info_numpy(li)
+        assert np.all(ci["status"] == conv) and np.all(ci["rel_res"] <= 1.5e-5)
+    fi = E.info_numpy(info)
+    log(f"  coarse iterations {[E.info_numpy(li)['iters'].tolist() for li in mg.last_info]}, "
+        f"fine {fi['iters'].tolist()}, fine residuals {fi['rel_res'].tolist()}")
+    assert np.all(fi["status"] == conv) and np.all(fi["rel_res"] <= 1e-5)
+    assert torch.isfinite(emd).all()
+    mg.close()
+    plan.close()
