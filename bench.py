@@ -5,15 +5,15 @@ A step is the whole path over one batch of synthetic gathers already resident in
 HBM: emd_decompose -> the PDHG-with-linesearch solve, started coarse-to-fine (the
 multi-grid strategy the paper applies to the EMD: the data restricted to coarser
 grids are solved first, and each solution, interpolated, starts the next finer
-solve; every level runs to a relative-residual stop rule, the coarse ones to 1.5
-times the fine one's) -> emd_adjoint_source.
+solve; every level runs to the relative-residual stop rule) -> emd_adjoint_source.
 The metric is PDHG cell-updates per second over all levels (sum of nr * nt *
 iterations, divided by the step time) for the batched FP32 solve; the EMD of the
 first gathers is checked against FP64 solves of them taken far past the stop rule
 (the accuracy the metric is quoted at), and the plain FP64 solve of the same gathers,
 one gather per plan, is timed beside it.  Further legs: the solve without the
 coarse start, plain fixed-step PDHG with two iterations per sweep, the 16 x 4000 x
-1600 batch at a fixed budget, the one-pass kernels, and the CPU oracle.
+1600 batch at a fixed budget and its whole misfit to the stop rule, the one-pass
+kernels, and the CPU oracle.
 
 Default workload: 64 gathers, nt ~ U{1500..3000}, nr ~ U{200..500}, 4-8 hyperbolic
 events (seed 3).  Prints one JSON line.
@@ -33,13 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+C5_FULL_MAX_ITER = 1000000
 BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi, R
 # Bytes crossing the L2 boundary per sweep over the algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest, per kernel; the traffic figure is null for any other
 # source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "0fd4afb31702c329",
-                    "ratio": {"k_sweep<float, false>": 1.0727, "k_sweep2<float>": 1.1618}}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "15db26d97cbeab68",
+                    "ratio": {"k_sweep<float, false>": 1.0732, "k_sweep2<float>": 1.1619}}
 
 
 def sweep_source_digest():
@@ -194,7 +195,7 @@ def main():
                     help="coarse levels that start the timed solve, finest first, each grouping FR "
                          "receivers by FT samples of the level above ('none': a plain solve; 'auto': "
                          "1x4,2x4 for c5, else 1x2,1x2,1x2)")
-    ap.add_argument("--coarse-tol-factor", type=float, default=1.5,
+    ap.add_argument("--coarse-tol-factor", type=float, default=1.0,
                     help="stop rule of the coarse levels over the fine one's")
     ap.add_argument("--fine-only-steps", type=int, default=1,
                     help="timed steps of the same solve without the coarse start (0: skip)")
@@ -207,6 +208,8 @@ def main():
                     help="timed steps of plain fixed-step PDHG, two iterations per sweep (0: skip)")
     ap.add_argument("--c5-iters", type=int, default=300,
                     help="fixed-budget leg on 16 gathers of 4000 x 1600 (0: skip)")
+    ap.add_argument("--c5-full", type=int, default=1,
+                    help="with the fixed-budget leg, also solve that batch to the stop rule once (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) 5 times, "
                          "to scale the HBM byte counters of a profiler run")
@@ -526,7 +529,49 @@ def main():
         log(f"16 x 4000 x 1600, {args.c5_iters} iterations: {step5:.1f} ms/step, sweeps at "
             f"{ach5:.0f} GB/s ({ach5 / HBM_PEAK_GBS:.3f} of peak)")
         plan5.close()
-        del pc5, po5, b5
+        del b5
+        if args.c5_full:
+            # the whole misfit of that batch and its adjoint source, to the stop rule,
+            # started coarse-to-fine (1 x 4, then 2 x 4): one run, its graph captures
+            # included (they are a few ms of it).  Its coarsest level needs up to ~330k
+            # iterations, hence a budget of its own.
+            p5f = E.SolverParams(precision=E.F32, tol_res=args.tol, max_iter=C5_FULL_MAX_ITER)
+            plan5f = E.Plan(desc5, pc5.numel(), p5f)
+            lv5 = parse_levels("auto", "c5")
+            mg5 = E.Multigrid(plan5f, lv5, coarse_tol_factor=args.coarse_tol_factor)
+            b5f = {"s": plan5f.empty(), "phi": plan5f.empty(), "psi": plan5f.empty(),
+                   "mass": torch.empty(len(desc5), 3, dtype=torch.float64, device=dev),
+                   "emd": torch.empty(len(desc5), dtype=torch.float64, device=dev),
+                   "info": torch.empty(len(desc5) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
+            torch.cuda.synchronize()
+            e0.record(stream)
+            _, info5 = run_step(E, plan5f, pc5, po5, b5f, mg5)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms5f = e0.elapsed_time(e1)
+            cu5f, msw5f, sw5f = step_stats(plan5f, mg5)
+            inf5 = E.info_numpy(info5)
+            ach5f = BYTES_PER_CELL_ITER["f32"] * cu5f / (msw5f / 1e3) / 1e9
+            extra["large_full_misfit"] = {
+                "workload": w5, "what": "decompose -> solve to the stop rule -> adjoint source, one run",
+                "stop_rule": f"||div u + s||/||s|| <= {args.tol:g}",
+                "coarse_levels": ",".join(f"{a}x{b}" for a, b in lv5),
+                "coarse_stop_rule": f"{args.tol * args.coarse_tol_factor:g}",
+                "ms": round(ms5f, 1), "value": cu5f / (ms5f / 1e3), "unit": "cell-updates/s",
+                "fine_iters_mean": float(inf5["iters"].mean()), "fine_iters_max": int(inf5["iters"].max()),
+                "coarse_iters_max": [int(E.info_numpy(i)["iters"].max()) for i in mg5.last_info],
+                "statuses": np.bincount(inf5["status"], minlength=7).tolist(),
+                "roofline": {"bound": "hbm", "achieved": round(ach5f, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(ach5f / HBM_PEAK_GBS, 4), "kernel": "k_sweep<float, false>",
+                             "launches": int(sw5f), "avg_launch_us": round(msw5f * 1e3 / max(sw5f, 1), 2),
+                             "algo_bytes_per_launch": int(BYTES_PER_CELL_ITER["f32"] * cu5f / max(sw5f, 1))}}
+            log(f"16 x 4000 x 1600 to the stop rule: {ms5f / 1e3:.2f} s, {cu5f / (ms5f / 1e3):.3e} cell-updates/s, "
+                f"fine iters mean {inf5['iters'].mean():.0f} max {inf5['iters'].max()}, "
+                f"statuses {np.bincount(inf5['status'], minlength=7).tolist()}")
+            mg5.close()
+            plan5f.close()
+            del b5f
+        del pc5, po5
 
     if args.fine_only_steps > 0 and mg is not None:
         # the same step with the solve started cold on the fine grid: the residual rule
