@@ -1104,11 +1104,13 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a, int parity)
 //
 // The dependency cone grows by one row and one sample per stage: a tile loads two
 // rows above and two below its own rows, and its halo lanes (0 and 57, four samples
-// each) cover the two samples either way.  The wave marches down; at step i (row i
-// just loaded) it forms P1 of row i, A_k, A_{k+1} and D1 of row i - 1, P2 of row
-// i - 1, then A_{k+2} and D2 of row i - 2.  Loaded rows sit in register sets indexed
-// by row mod 4 (the next row loads into the set of row i - 3), computed rows in sets
-// indexed by row mod 2; the loop is unrolled by four so every index is static.
+// each) cover the two samples either way.  On even strips the wave marches down; at
+// step i (row i just loaded) it forms P1 of row i, A_k, A_{k+1} and D1 of row i - 1,
+// P2 of row i - 1, then A_{k+2} and D2 of row i - 2.  Loaded rows sit in register sets
+// indexed by row mod 4 (the next row loads into the set of row i - 3), computed rows
+// in sets indexed by row mod 2; the loop is unrolled by four so every index is static.
+// Odd strips march up (Pipe2Up), so that neighbouring strips read their shared rows
+// together.
 // ======================================================================================
 
 struct Decision2 {
@@ -1338,9 +1340,112 @@ struct Pipe2 {
     }
 };
 
+// The upward march of the two-iteration sweep, used on odd strips so that the two
+// tiles at every strip boundary read their shared rows (two either side) at about the
+// same time, as in PipeUp.  Row r's primal update needs phi of row r - 1 (the
+// backward x-difference) and its residual the flux of row r + 1 (the forward
+// difference), so marching up from the last loaded row each stage runs one row
+// behind the one before it: at step i (row i just loaded) the wave forms P1 of row
+// i + 1, A_k, A_{k+1} and D1 of row i + 1, then P2, A_{k+2} and D2 of row i + 2.
+// Every row is computed by the same calls on the same operands as in Pipe2, so the
+// fields are bitwise the same; only the order in which the stop rule's sums add the
+// rows differs.  Register sets: loaded rows by (ilast - row) mod 4, computed rows by
+// parity of that, as in Pipe2.  Rows above the grid (i < 0) are virtual: nothing is
+// loaded for them and their weights in the operators are zero.
+template <typename T, bool EDGE>
+struct Pipe2Up : Pipe2<T, EDGE> {
+    using B = Pipe2<T, EDGE>;
+    using B::c;
+    using B::LX;
+    using B::LT;
+    using B::LP;
+    using B::LS;
+    using B::P1X;
+    using B::P1T;
+    using B::A1;
+    using B::D1;
+    using B::P2X;
+    using B::P2T;
+    static constexpr int V = Vec<T>::N;
+
+    __device__ explicit Pipe2Up(const TileCtx<T>& ctx) : B(ctx) {}
+
+    // rows outside [ibeg, ilast] go out of range instead of to memory
+    __device__ __forceinline__ void load_row(int i, T (&ux)[V], T (&ut)[V], T (&ph)[V], T (&sv)[V])
+    {
+        const uint32_t o = (i >= c.ibeg && i <= c.ilast) ? c.vb_ld + (uint32_t)i * c.row_bytes : OOB;
+        bload(c.uxi, o, ux);
+        bload(c.uti, o, ut);
+        bload(c.phi_i, o, ph);
+        bload(c.si, o, sv);
+    }
+
+    // step on row i; S = (ilast - i) mod 4; TWO: two iterations (else one)
+    template <int S, bool TWO>
+    __device__ __forceinline__ void step(int i)
+    {
+        constexpr int C = S, U1 = (S + 3) & 3, U2 = (S + 2) & 3, NX = (S + 1) & 3;
+        constexpr int P = S & 1, Q = P ^ 1;  // computed rows: i + 1 in set Q, i + 2 in set P
+        load_row(i - 1, LX[NX], LT[NX], LP[NX], LS[NX]);
+        // P1 of row i + 1 (phi_k of rows i + 1 and i)
+        const int m = i + 1;
+        this->prox_row(LX[U1], LT[U1], LP[U1], LP[C], m > 0, P1X[Q], P1T[Q]);
+        // A_k and A_{k+1} of row i + 1 (fluxes of rows i + 1 and i + 2), then D1
+        const bool nxt = m + 1 < c.nr, prv = m > 0;
+        T a0[V], a1[V];
+        div_row<T, EDGE>(c, nxt, prv, LX[U1], LX[U2], LT[U1], lane_next(LT[U1][0]), LS[U1], a0);
+        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], lane_next(P1T[Q][0]), LS[U1], a1);
+        this->dual_row(a1, a0, LP[U1], D1[Q]);
+#pragma unroll
+        for (int k = 0; k < V; ++k) A1[Q][k] = a1[k];
+        if constexpr (!TWO) {
+            this->store(c.uxo, this->store_off(m), P1X[Q]);
+            this->store(c.uto, this->store_off(m), P1T[Q]);
+            this->store(c.phio, this->store_off(m), D1[Q]);
+            this->sum_flux(m, P1X[Q], P1T[Q]);
+            this->sum_res(m, a1);
+        } else {
+            // P2 of row i + 2 (phi_{k+1} of rows i + 2 and i + 1)
+            const int m2 = i + 2;
+            this->prox_row(P1X[P], P1T[P], D1[P], D1[Q], m2 > 0, P2X[P], P2T[P]);
+            this->store(c.uxo, this->store_off(m2), P2X[P]);
+            this->store(c.uto, this->store_off(m2), P2T[P]);
+            this->sum_flux(m2, P2X[P], P2T[P]);
+            // A_{k+2} of row i + 2 (P2 of rows i + 2 and i + 3) and D2
+            T a2[V], d2[V];
+            div_row<T, EDGE>(c, m2 + 1 < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], lane_next(P2T[P][0]),
+                             LS[U2], a2);
+            this->dual_row(a2, A1[P], D1[P], d2);
+            this->store(c.phio, this->store_off(m2), d2);
+            this->sum_res(m2, a2);
+        }
+    }
+
+    // steps from the last loaded row up to (and including) row iend_up
+    template <bool TWO>
+    __device__ __forceinline__ void run_up(int iend_up)
+    {
+        load_row(c.ilast, LX[0], LT[0], LP[0], LS[0]);
+        int i = c.ilast;
+        for (; i - 3 >= iend_up; i -= 4) {
+            step<0, TWO>(i);
+            step<1, TWO>(i - 1);
+            step<2, TWO>(i - 2);
+            step<3, TWO>(i - 3);
+        }
+        if (i >= iend_up) {
+            step<0, TWO>(i--);
+            if (i >= iend_up) {
+                step<1, TWO>(i--);
+                if (i >= iend_up) step<2, TWO>(i--);
+            }
+        }
+    }
+};
+
 template <typename T, bool EDGE>
 __device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
-                            double* red)
+                            double* red, bool up)
 {
     constexpr int V = Vec<T>::N;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1388,23 +1493,40 @@ __device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherM
     c.theta = T(1.0);
     c.alpha = T(d.alpha);
     c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
-    Pipe2<T, EDGE> P(c);
     double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
-    if (d.steps == 2) {
-        // the last own row's D2 needs the step two rows below it (rows past the grid
-        // are virtual: nothing is loaded there and their weights are zero)
-        P.iend = c.rend + 1;
-        P.template run<true>();
+    double aa, l1, l2;
+    // one pipeline object for both directions: with the direction a run-time (wave-
+    // uniform) branch the kernel keeps the register count of one direction (118
+    // VGPRs in FP32, four waves per SIMD) where two instantiations took 140
+    Pipe2Up<T, EDGE> P(c);
+    if (up) {
+        // the first own row's outputs come from the step one (P1, D1) or two (P2, D2)
+        // rows above it
+        if (d.steps == 2) P.template run_up<true>(c.r0 - 2);
+        else P.template run_up<false>(c.r0 - 1);
+        aa = P.aa;
+        l1 = P.l1;
+        l2 = P.l2;
     } else {
-        P.iend = c.rend;
-        P.template run<false>();
+        if (d.steps == 2) {
+            // the last own row's D2 needs the step two rows below it (rows past the
+            // grid are virtual: nothing is loaded there and their weights are zero)
+            P.iend = c.rend + 1;
+            P.template run<true>();
+        } else {
+            P.iend = c.rend;
+            P.template run<false>();
+        }
+        aa = P.aa;
+        l1 = P.l1;
+        l2 = P.l2;
     }
     double r[NPART];
 #pragma unroll
     for (int m = 0; m < NPART; ++m) r[m] = 0.0;
-    r[0] = wave_sum(P.aa);
-    r[6] = wave_sum(P.l1);
-    r[7] = wave_sum(P.l2);
+    r[0] = wave_sum(aa);
+    r[6] = wave_sum(l1);
+    r[7] = wave_sum(l2);
     if (lane == 0) {
 #pragma unroll
         for (int m = 0; m < NPART; ++m) dst[m] = r[m];
@@ -1455,8 +1577,10 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
     }
     const int pb = parity;
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
-    if (edge) sweep_tile2<T, true>(a, tl, gm, parity, pb, w, xred);
-    else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred);
+    // odd strips march up
+    const bool up = ((tl.r0 / gm.rows) & 1) != 0;
+    if (edge) sweep_tile2<T, true>(a, tl, gm, parity, pb, w, xred, up);
+    else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred, up);
 }
 
 template <typename T>

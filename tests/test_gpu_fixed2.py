@@ -64,8 +64,9 @@ def test_two_iterations_per_sweep_equal_one_iteration_per_sweep(precision, K):
     log(f"  precision={precision} K={K}: sweeps one/two {out['one', 16, 'sweeps']}/{out['two', 16, 'sweeps']}")
     for rows in (16, 1, 3):
         emd, phi, u, info = out["two", rows]
-        # the two-iteration sweep marches every tile down: any tiling gives its bits,
-        # which are those of the one-iteration sweep
+        # the two-iteration sweep marches even strips down and odd strips up with the
+        # same per-row arithmetic: any tiling gives its bits, which are those of the
+        # one-iteration sweep
         np.testing.assert_array_equal(phi, ref[1], err_msg=f"two, rows {rows}")
         np.testing.assert_array_equal(u, ref[2], err_msg=f"two, rows {rows}")
         np.testing.assert_array_equal(info["iters"], ref[3]["iters"])
