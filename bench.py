@@ -11,7 +11,7 @@ iterations, divided by the step time) for the batched FP32 solve; the EMD of the
 first gathers is checked against FP64 solves of them taken far past the stop rule
 (the accuracy the metric is quoted at), and the plain FP64 solve of the same gathers,
 one gather per plan, is timed beside it.  Further legs: the solve without the
-coarse start, plain fixed-step PDHG with two iterations per sweep, the 16 x 4000 x
+coarse start, plain fixed-step PDHG with three iterations per sweep, the 16 x 4000 x
 1600 batch at a fixed budget and its whole misfit to the stop rule, the one-pass
 kernels, and the CPU oracle.
 
@@ -205,7 +205,10 @@ def main():
     ap.add_argument("--gate-ref-tol", type=float, default=2e-7,
                     help="residual the FP64 reference is solved to")
     ap.add_argument("--fixed-steps", type=int, default=1,
-                    help="timed steps of plain fixed-step PDHG, two iterations per sweep (0: skip)")
+                    help="timed steps of plain fixed-step PDHG, several iterations per sweep (0: skip)")
+    ap.add_argument("--fixed-ips", type=int, default=3, choices=[2, 3],
+                    help="iterations per sweep of the fixed-step leg")
+    ap.add_argument("--fixed-rows", type=int, default=24, help="tile height of the fixed-step leg's fine plan")
     ap.add_argument("--c5-iters", type=int, default=300,
                     help="fixed-budget leg on 16 gathers of 4000 x 1600 (0: skip)")
     ap.add_argument("--c5-full", type=int, default=1,
@@ -443,14 +446,17 @@ def main():
 
     if args.fixed_steps > 0:
         # Plain PDHG with the fixed steps alpha_1, beta_1 = delta alpha_1 (Section 2.2
-        # before the linesearch): no per-iteration decision, so one sweep runs two
-        # iterations (read u, phi, s; write u, phi: 28 B per cell per sweep), to the
-        # same stop rule, with its own roofline and accuracy against the reference
-        pf = dataclasses.replace(params, ls_mode=E.LS_FIXED, iters_per_sweep=2, max_iter=4 * args.max_iter)
+        # before the linesearch): no per-iteration decision, so one sweep runs K
+        # iterations (read u, phi, s; write u, phi: 28 B per cell per sweep, 28 / K per
+        # iteration), to the same stop rule, checked every 3K iterations, with its own
+        # roofline and accuracy against the reference
+        K = args.fixed_ips
+        pf = dataclasses.replace(params, ls_mode=E.LS_FIXED, iters_per_sweep=K, check_every=3 * K,
+                                 max_iter=4 * args.max_iter)
         planf = E.Plan(desc, len(pcal_h), pf)
-        if rows:
-            planf.set_gather_tiling(rows)
-        mgf = E.Multigrid(planf, levels, coarse_tol_factor=args.coarse_tol_factor) if levels else None
+        planf.set_tiling(args.fixed_rows)
+        mgf = E.Multigrid(planf, levels, coarse_rows=16,
+                          coarse_tol_factor=args.coarse_tol_factor) if levels else None
         run_step(E, planf, pcal, pobs, bufs, mgf)  # captures the graphs
         torch.cuda.synchronize()
         cuf, msf, swf = 0, 0.0, 0
@@ -465,25 +471,26 @@ def main():
         torch.cuda.synchronize()
         stepf = e0.elapsed_time(e1) / args.fixed_steps
         inff = E.info_numpy(info_f)
-        # algorithmic bytes: 28 per cell per sweep of two iterations (14 per iteration)
-        achf = 14 * cuf / (msf / 1e3) / 1e9
-        extra["plain_pdhg_two_iterations_per_sweep"] = {
-            "what": "plain PDHG with fixed steps, two iterations per HBM pass, FP32, same coarse start "
+        kname = f"k_sweep{K}<float>"
+        achf = 28.0 / K * cuf / (msf / 1e3) / 1e9
+        extra["plain_pdhg_fixed_steps"] = {
+            "what": f"plain PDHG with fixed steps, {K} iterations per HBM pass, FP32, same coarse start "
                     "and stop rule",
+            "iterations_per_sweep": K, "tile_rows": args.fixed_rows,
             "value": cuf / args.fixed_steps / (stepf / 1e3), "unit": "cell-updates/s",
             "ms_per_step": round(stepf, 3), "speedup_vs_linesearch_step": round(ms_per_step / stepf, 3),
             "iters_mean": float(inff["iters"].mean()), "iters_max": int(inff["iters"].max()),
             "statuses": np.bincount(inff["status"], minlength=7).tolist(),
             "roofline": {"bound": "hbm", "achieved": round(achf, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achf / HBM_PEAK_GBS, 4), "kernel": "k_sweep2<float>",
-                         "traffic": round(MEASURED_TRAFFIC["ratio"]["k_sweep2<float>"] * achf, 1) if measured else None,
+                         "frac": round(achf / HBM_PEAK_GBS, 4), "kernel": kname,
+                         "traffic": round(MEASURED_TRAFFIC["ratio"][kname] * achf, 1)
+                         if measured and kname in MEASURED_TRAFFIC["ratio"] else None,
                          "launches": int(swf), "avg_launch_us": round(msf * 1e3 / max(swf, 1), 2),
-                         "algo_bytes_per_launch": int(14 * cuf / max(swf, 1))}}
+                         "algo_bytes_per_launch": int(28.0 / K * cuf / max(swf, 1))}}
         if ref is not None:
             ef = emd_f.cpu().numpy()[:len(ref)]
-            extra["plain_pdhg_two_iterations_per_sweep"]["emd_rel_err_vs_ref_max"] = float(
-                np.max(np.abs(ef / ref - 1)))
-        log(f"fixed steps, two iterations per sweep: {stepf:.1f} ms/step ({ms_per_step / stepf:.2f}x the "
+            extra["plain_pdhg_fixed_steps"]["emd_rel_err_vs_ref_max"] = float(np.max(np.abs(ef / ref - 1)))
+        log(f"fixed steps, {K} iterations per sweep: {stepf:.1f} ms/step ({ms_per_step / stepf:.2f}x the "
             f"linesearch), iters mean {inff['iters'].mean():.0f}, sweeps at {achf:.0f} GB/s")
         if mgf is not None:
             mgf.close()

@@ -121,11 +121,11 @@ typedef struct {
  *     at capture (keep the plan, and its tiling, while the graph may run).
  *     emd_plan_query and emd_solver_state synchronise the device before reading
  *     the state such a solve left.
- *   iters_per_sweep: 1 (or 0): one PDHG iteration per sweep of the fields; 2: with
- *     EMD_LS_FIXED only, two iterations per sweep (one HBM pass reads u, phi, s and
- *     writes u, phi for two iterations; the fields are bitwise those of one
- *     iteration per sweep), with check_every even: the stop rule is checked on even
- *     iteration counts. */
+ *   iters_per_sweep: 1 (or 0): one PDHG iteration per sweep of the fields; K = 2 or
+ *     3: with EMD_LS_FIXED only, K iterations per sweep (one HBM pass reads u, phi, s
+ *     and writes u, phi for K iterations; the fields are bitwise those of one
+ *     iteration per sweep), with check_every a multiple of K: the stop rule is
+ *     checked on multiples of K.  K = 3 needs EMD_F32. */
 typedef struct {
     double eps, xi, zeta, delta, alpha1, alpha_max_factor, tol_res, mass_tol;
     int32_t max_iter, check_every, max_ls_trials, ls_mode;

@@ -142,11 +142,15 @@ emd_status validate_params(const emd_params* p)
     if (p->precision != EMD_F32 && p->precision != EMD_F64) return bad("unknown precision");
     // a solve reads the newest state from buffer 0, so every chunk is an even number
     // of sweeps; 0 selects the fixed-budget solve (no reads between sweeps)
-    if (p->iters_per_sweep < 0 || p->iters_per_sweep > 2) return bad("iters_per_sweep must be 0, 1 or 2");
-    if (p->iters_per_sweep == 2 && p->ls_mode != EMD_LS_FIXED)
-        return bad("two iterations per sweep need fixed steps (ls_mode EMD_LS_FIXED)");
-    if (p->iters_per_sweep == 2 && (p->check_every & 1))
-        return bad("two iterations per sweep check the stop rule on even counts: check_every must be even");
+    if (p->iters_per_sweep < 0 || p->iters_per_sweep > 3) return bad("iters_per_sweep must be 0, 1, 2 or 3");
+    if (p->iters_per_sweep >= 2 && p->ls_mode != EMD_LS_FIXED)
+        return bad("two or three iterations per sweep need fixed steps (ls_mode EMD_LS_FIXED)");
+    if (p->iters_per_sweep >= 2 && p->check_every % p->iters_per_sweep != 0)
+        return bad("K iterations per sweep check the stop rule on multiples of K: check_every must be one");
+    // a sweep of K iterations reaches K samples past its tile in time, which the halo
+    // lanes carry: four FP32 samples each, two FP64 ones
+    if (p->iters_per_sweep == 3 && p->precision == EMD_F64)
+        return bad("three iterations per sweep need FP32 fields (an FP64 lane carries two halo samples)");
     if (p->sweeps_per_sync != 0 &&
         (p->sweeps_per_sync < 2 || p->sweeps_per_sync > 4096 || (p->sweeps_per_sync & 1)))
         return bad("sweeps_per_sync must be 0, or even and in [2, 4096]");
@@ -307,7 +311,7 @@ SweepArgs<T> sweep_args(emd_plan* plan, const SolveScalars& sc)
     }
     a.done = plan->d_done;
     a.l1 = sc.ls_mode == LS_L1;
-    a.two = sc.ls_mode == LS_FIXED && plan->params.iters_per_sweep == 2;
+    a.ips = sc.ls_mode == LS_FIXED && plan->params.iters_per_sweep >= 2 ? plan->params.iters_per_sweep : 0;
     a.sc = sc;
     return a;
 }
@@ -476,10 +480,12 @@ emd_status solve_impl(emd_plan* plan, const void* s, void* u, void* phi, int war
     // a gather needs iters + 1 sweeps, the last one applying the final dual step;
     // the l1 test may add an evaluation sweep per NL1 failed backtracking trials
     const int64_t evals = ls_mode == LS_L1 ? plan->params.max_ls_trials / NL1 + 1 : 0;
-    // two iterations per sweep: max_iter / 2 sweeps of work (one more to align an odd
-    // resumed count), then the sweep that takes the last decision
-    const int64_t max_sweeps = sa.two ? round_up(((int64_t)plan->params.max_iter + 1) / 2 + 2, 2)
-                                      : round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
+    // K iterations per sweep: ceil(max_iter / K) sweeps of work (one more to align a
+    // resumed count that is not a multiple of K), then the sweep that takes the last
+    // decision
+    const int64_t K = sa.ips;
+    const int64_t max_sweeps = K ? round_up(((int64_t)plan->params.max_iter + K - 1) / K + 2, 2)
+                                 : round_up(((int64_t)plan->params.max_iter + 2) * (1 + evals), 2);
     plan->resume_iters.clear();
     if (h_resume)
         for (int g = 0; g < plan->ngather; ++g) plan->resume_iters.push_back(h_resume[g].iters);

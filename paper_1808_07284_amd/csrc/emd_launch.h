@@ -22,7 +22,8 @@ struct SweepArgs {
     GState* gst[2];        // [ngather], by sweep parity
     int32_t* done;         // gathers that have finished
     int32_t l1;            // 1: the l1 form of the linesearch test
-    int32_t two;           // 1: fixed-step PDHG, two iterations per sweep (k_sweep2)
+    int32_t ips;           // fixed-step PDHG with 2 (k_sweep2) or 3 (k_sweep3) iterations
+                           // per sweep; 0: one iteration per sweep (k_sweep)
     SolveScalars sc;
 };
 

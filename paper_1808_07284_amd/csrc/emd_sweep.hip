@@ -1118,12 +1118,13 @@ struct Decision2 {
     int steps;  // PDHG iterations this sweep applies to the gather (0: none)
 };
 
-// The gather's decision at the start of a sweep: the stop rule on the sums of the
-// previous sweep (which describe u_k, the flux this sweep reads), then how many
-// iterations this sweep runs: two, or one to bring an odd count (a resumed
-// checkpoint) back to even, or to end at max_iter.  Checks fall on even counts.
-template <typename T>
-__device__ Decision2 decide_fixed2(const SweepArgs<T>& a, int p, int g, const GatherMeta& gm, bool writer,
+// The gather's decision at the start of a sweep of K iterations: the stop rule on the
+// sums of the previous sweep (which describe u_k, the flux this sweep reads), then how
+// many iterations this sweep runs: K, or fewer to bring a count that is not a
+// multiple of K (a resumed checkpoint) back to one, or to end at max_iter.  Checks
+// fall on multiples of K.
+template <typename T, int K>
+__device__ Decision2 decide_fixedk(const SweepArgs<T>& a, int p, int g, const GatherMeta& gm, bool writer,
                                    int pb, int w, double* red)
 {
     const GState* __restrict__ sin = a.gst[p] + g;
@@ -1168,7 +1169,7 @@ __device__ Decision2 decide_fixed2(const SweepArgs<T>& a, int p, int g, const Ga
         return d;
     }
     st.started = 1;
-    int steps = (st.iters & 1) ? 1 : 2;
+    int steps = K - st.iters % K;
     if (steps > sc.max_iter - st.iters) steps = max(sc.max_iter - st.iters, 1);
     st.iters += steps;
     st.ubuf = pb ^ 1;
@@ -1487,7 +1488,7 @@ __device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherM
     c.ri = c.si;
     c.ro = c.phio;
 
-    const Decision2 d = decide_fixed2<T>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
+    const Decision2 d = decide_fixedk<T, 2>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
     if (d.steps == 0) return;
     c.beta = T(d.beta);
     c.theta = T(1.0);
@@ -1583,10 +1584,273 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
     else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred, up);
 }
 
+// ======================================================================================
+// Plain PDHG with fixed steps, three iterations per HBM pass (iters_per_sweep = 3): the
+// two-iteration pipeline with a third stage.  Stage s (1, 2, 3) forms, at step i, the
+// primal update P_s of row i - s + 1 and the residuals A_{k+s-1}, A_{k+s} and dual
+// update D_s of row i - s, each from the stage before it one step earlier:
+//   P1 of row i; A_k, A_{k+1}, D1 of row i - 1;
+//   P2 of row i - 1; A_{k+2}, D2 of row i - 2;
+//   P3 of row i - 2; A_{k+3}, D3 of row i - 3,
+// with the calls and operands of the one-iteration sweep, so the fields are bitwise
+// its fields.  A tile loads three rows above and three below its own rows (its halo
+// lanes' four FP32 samples cover the three samples either way; FP64 lanes hold two,
+// so the plan rejects three iterations per sweep in FP64).  u^x, u^t, phi of loaded
+// rows sit in sets by row mod 4 (rows i - 1, i, and i + 1 in flight); s is needed
+// three rows back, so row i + 1's s is loaded at the end of step i, into the set of
+// row i - 3 that stage 3 has just read, and first used two steps later.  A sweep of
+// one or two iterations (to realign a count, or at max_iter) runs the first stages
+// only, with the one- or two-row halo.  The same 28 bytes per cell as the
+// two-iteration sweep now carry three iterations (9.3 per iteration).
+// ======================================================================================
+
+template <typename T, bool EDGE>
+struct Pipe3 : Pipe2<T, EDGE> {
+    using B = Pipe2<T, EDGE>;
+    using B::c;
+    using B::LX;
+    using B::LT;
+    using B::LP;
+    using B::LS;
+    using B::P1X;
+    using B::P1T;
+    using B::A1;
+    using B::D1;
+    using B::P2X;
+    using B::P2T;
+    static constexpr int V = Vec<T>::N;
+    T A2[2][V], D2[2][V];    // A_{k+2}, phi_{k+2}: rows i - 2 and i - 3
+    T P3X[2][V], P3T[2][V];  // u_{k+3}: rows i - 2 and i - 3
+
+    __device__ explicit Pipe3(const TileCtx<T>& ctx) : B(ctx)
+    {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            zero(A2[b]); zero(D2[b]); zero(P3X[b]); zero(P3T[b]);
+        }
+    }
+
+    // rows outside [ibeg, ilast] go out of range instead of to memory
+    __device__ __forceinline__ uint32_t roff(int i) const
+    {
+        return (i >= c.ibeg && i <= c.ilast) ? c.vb_ld + (uint32_t)i * c.row_bytes : OOB;
+    }
+    __device__ __forceinline__ void load_f(int i, T (&ux)[V], T (&ut)[V], T (&ph)[V])
+    {
+        const uint32_t o = roff(i);
+        bload(c.uxi, o, ux);
+        bload(c.uti, o, ut);
+        bload(c.phi_i, o, ph);
+    }
+    __device__ __forceinline__ void load_s(int i, T (&sv)[V]) { bload(c.si, roff(i), sv); }
+
+    // step on row i; S = (i - ibeg) mod 4; K: iterations this sweep runs (1, 2 or 3)
+    template <int S, int K>
+    __device__ __forceinline__ void step(int i)
+    {
+        constexpr int C = S, PV = (S + 3) & 3, NX = (S + 1) & 3;
+        constexpr int M1 = PV, M2 = (S + 2) & 3, M3 = (S + 1) & 3;  // s of rows i - 1, i - 2, i - 3
+        constexpr int P = S & 1, Q = P ^ 1;
+        load_f(i + 1, LX[NX], LT[NX], LP[NX]);
+        // stage 1: P1 of row i, then A_k, A_{k+1} and D1 of row i - 1
+        this->prox_row(LX[C], LT[C], LP[C], LP[PV], i > 0, P1X[P], P1T[P]);
+        const int m = i - 1;
+        const bool nxt = i < c.nr, prv = m > 0;
+        T a0[V], a1[V];
+        div_row<T, EDGE>(c, nxt, prv, LX[PV], LX[C], LT[PV], lane_next(LT[PV][0]), LS[M1], a0);
+        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], lane_next(P1T[Q][0]), LS[M1], a1);
+        this->dual_row(a1, a0, LP[PV], D1[Q]);
+#pragma unroll
+        for (int k = 0; k < V; ++k) A1[Q][k] = a1[k];
+        if constexpr (K == 1) {
+            this->store(c.uxo, this->store_off(m), P1X[Q]);
+            this->store(c.uto, this->store_off(m), P1T[Q]);
+            this->store(c.phio, this->store_off(m), D1[Q]);
+            this->sum_flux(m, P1X[Q], P1T[Q]);
+            this->sum_res(m, a1);
+        } else {
+            // stage 2: P2 of row i - 1, then A_{k+2} and D2 of row i - 2
+            this->prox_row(P1X[Q], P1T[Q], D1[Q], D1[P], m > 0, P2X[Q], P2T[Q]);
+            const int m2 = i - 2;
+            T a2[V];
+            div_row<T, EDGE>(c, m < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], lane_next(P2T[P][0]), LS[M2], a2);
+            if constexpr (K == 2) {
+                this->store(c.uxo, this->store_off(m), P2X[Q]);
+                this->store(c.uto, this->store_off(m), P2T[Q]);
+                this->sum_flux(m, P2X[Q], P2T[Q]);
+                T d2[V];
+                this->dual_row(a2, A1[P], D1[P], d2);
+                this->store(c.phio, this->store_off(m2), d2);
+                this->sum_res(m2, a2);
+            } else {
+                this->dual_row(a2, A1[P], D1[P], D2[P]);
+#pragma unroll
+                for (int k = 0; k < V; ++k) A2[P][k] = a2[k];
+                // stage 3: P3 of row i - 2, then A_{k+3} and D3 of row i - 3
+                this->prox_row(P2X[P], P2T[P], D2[P], D2[Q], m2 > 0, P3X[P], P3T[P]);
+                this->store(c.uxo, this->store_off(m2), P3X[P]);
+                this->store(c.uto, this->store_off(m2), P3T[P]);
+                this->sum_flux(m2, P3X[P], P3T[P]);
+                const int m3 = i - 3;
+                T a3[V], d3[V];
+                div_row<T, EDGE>(c, m2 < c.nr, m3 > 0, P3X[Q], P3X[P], P3T[Q], lane_next(P3T[Q][0]),
+                                 LS[M3], a3);
+                this->dual_row(a3, A2[Q], D2[Q], d3);
+                this->store(c.phio, this->store_off(m3), d3);
+                this->sum_res(m3, a3);
+            }
+        }
+        // s of row i + 1, into the set stage 3 read above (first used at step i + 2)
+        load_s(i + 1, LS[NX]);
+    }
+
+    template <int K>
+    __device__ __forceinline__ void run()
+    {
+        load_f(c.ibeg, LX[0], LT[0], LP[0]);
+        load_s(c.ibeg, LS[0]);
+        const int iend = this->iend;
+        int i = c.ibeg;
+        for (; i + 3 <= iend; i += 4) {
+            step<0, K>(i);
+            step<1, K>(i + 1);
+            step<2, K>(i + 2);
+            step<3, K>(i + 3);
+        }
+        if (i <= iend) {
+            step<0, K>(i++);
+            if (i <= iend) {
+                step<1, K>(i++);
+                if (i <= iend) step<2, K>(i++);
+            }
+        }
+    }
+};
+
+template <typename T, bool EDGE>
+__device__ void sweep_tile3(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
+                            double* red)
+{
+    constexpr int V = Vec<T>::N;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int q = p ^ 1, qb = pb ^ 1;
+    const Decision2 d = decide_fixedk<T, 3>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
+    if (d.steps == 0) return;
+    TileCtx<T> c;
+    c.nr = gm.nr;
+    c.ld = gm.ld;
+    const int nt = gm.nt;
+    c.r0 = tl.r0;
+    c.rend = min(tl.r0 + gm.rows, gm.nr);
+    // a sweep of K iterations reads K rows above and below the strip
+    c.ibeg = max(tl.r0 - d.steps, 0);
+    c.ilast = min(c.rend + d.steps - 1, gm.nr - 1);
+    const int j0 = tl.c0 - V + V * lane;
+    const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
+    c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int j = j0 + k;
+        c.inb[k] = (j >= 0) && (j < nt);
+        c.jgt0[k] = j > 0;
+        c.jlt[k] = j + 1 < nt;
+    }
+    c.idx = T(1.0 / gm.dx);
+    c.idt = T(1.0 / gm.dt);
+    c.row_bytes = (uint32_t)(gm.ld * sizeof(T));
+    c.vb_ld = lane_load ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    c.vb_st = c.lane_out ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
+    const int bytes = (int)((int64_t)gm.nr * gm.ld * sizeof(T));
+    auto rs = [&](const T* f) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f + gm.poff), 0, bytes, 0x00020000);
+    };
+    c.uxi = rs(a.ux[pb]);
+    c.uti = rs(a.ut[pb]);
+    c.phi_i = rs(a.phi[pb]);
+    c.si = rs(a.s);
+    c.uxo = rs(a.ux[qb]);
+    c.uto = rs(a.ut[qb]);
+    c.phio = rs(a.phi[qb]);
+    c.ri = c.si;
+    c.ro = c.phio;
+    c.beta = T(d.beta);
+    c.theta = T(1.0);
+    c.alpha = T(d.alpha);
+    c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    Pipe3<T, EDGE> P(c);
+    // the last own row's D_K comes from the step K - 1 rows below it (rows past the
+    // grid are virtual: nothing is loaded there and their weights are zero)
+    P.iend = c.rend + d.steps - 1;
+    if (d.steps == 3) P.template run<3>();
+    else if (d.steps == 2) P.template run<2>();
+    else P.template run<1>();
+    double r[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) r[m] = 0.0;
+    r[0] = wave_sum(P.aa);
+    r[6] = wave_sum(P.l1);
+    r[7] = wave_sum(P.l2);
+    if (lane == 0) {
+        double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) dst[m] = r[m];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
+{
+    constexpr int V = Vec<T>::N;
+    constexpr int WPB = 256 / WAVE;
+    __shared__ double red[WPB * NPART];
+    const int w = uniform((int)threadIdx.x / WAVE);
+    const int first = uniform(xcd_logical_block() * WPB);
+    const int tid = first + w;
+    if (tid >= a.ntiles) return;
+    // the four waves of a block on one running gather share its decision sums (as in
+    // k_sweep; every wave of such a block reaches the one barrier)
+    int gb = -1;
+    bool split = first + WPB <= a.ntiles;
+    for (int k = 0; k < WPB && split; ++k) {
+        const int gk = uniform(a.tiles[first + k].g);
+        if (gk < 0) continue;
+        if (gb < 0) gb = gk;
+        else if (gk != gb) split = false;
+    }
+    if (gb < 0) split = false;
+    if (split) {
+        const GState* sb = a.gst[parity] + gb;
+        split = uniform(sb->status) == ST_RUNNING && uniform(sb->started) != 0;
+    }
+    const Tile tl = a.tiles[tid];
+    const int g = uniform(tl.g);
+    if (g < 0) {
+        if (split) {
+            const GatherMeta mb = a.meta[gb];
+            double s[NPART];
+            decision_sums<NPART>(a.part[parity] + (int64_t)mb.tile_base * NPART, mb.ntiles, w, red, s);
+        }
+        return;
+    }
+    double* const xred = split ? red : nullptr;
+    const GatherMeta gm = a.meta[g];
+    const GState* gs = a.gst[parity] + g;
+    if (gs->status != ST_RUNNING) {
+        if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0) a.gst[parity ^ 1][g] = *gs;
+        return;
+    }
+    const int pb = parity;
+    const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
+    if (edge) sweep_tile3<T, true>(a, tl, gm, parity, pb, w, xred);
+    else sweep_tile3<T, false>(a, tl, gm, parity, pb, w, xred);
+}
+
 template <typename T>
 void launch_sweep(const SweepArgs<T>& a, int parity, int grid, hipStream_t stream)
 {
-    if (a.two)
+    if (a.ips == 3)
+        hipLaunchKernelGGL((k_sweep3<T>), dim3(grid), dim3(256), 0, stream, a, parity);
+    else if (a.ips == 2)
         hipLaunchKernelGGL((k_sweep2<T>), dim3(grid), dim3(256), 0, stream, a, parity);
     else if (a.l1)
         hipLaunchKernelGGL((k_sweep<T, true>), dim3(grid), dim3(256), 0, stream, a, parity);

@@ -83,9 +83,12 @@ def _create(L, lib, descs, batch_len, **over):
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 1}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 3}, 1),  # chunks hold whole sweep pairs
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": -2}, 1),
-    ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 3}, 1),
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 4, "ls_mode": 2}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 2}, 1),                       # needs fixed steps
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 3}, 1),                       # needs fixed steps
     ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 2, "ls_mode": 2, "check_every": 5}, 1),  # odd checks
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 3, "ls_mode": 2, "check_every": 10}, 1),  # not x3
+    ([(2, 5, 1.0, 1.0, 0)], 10, {"iters_per_sweep": 3, "ls_mode": 2, "check_every": 12, "precision": 1}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"sweeps_per_sync": 4098}, 1),
     ([(2, 5, 1.0, 1.0, 0)], 10, {"ls_mode": 3}, 1),         # unknown linesearch test
     # a field region of a gather (nr rows of nt rounded up to 32) may not pass 1 GiB

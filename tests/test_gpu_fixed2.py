@@ -41,13 +41,16 @@ def _run(plan, s, mass, **kw):
     return emd.cpu().numpy(), phi.cpu().numpy(), u.cpu().numpy(), E.info_numpy(info)
 
 
-@pytest.mark.parametrize("precision", [E.F32, E.F64])
-@pytest.mark.parametrize("K", [300, 301])
-def test_two_iterations_per_sweep_equal_one_iteration_per_sweep(precision, K):
+@pytest.mark.parametrize("precision,ips,K", [(E.F32, 2, 300), (E.F32, 2, 301), (E.F64, 2, 300), (E.F64, 2, 301),
+                                             (E.F32, 3, 300), (E.F32, 3, 301), (E.F32, 3, 302)])
+def test_two_iterations_per_sweep_equal_one_iteration_per_sweep(precision, ips, K):
+    # ips iterations per sweep (2, or 3 in FP32); a count that is not a multiple of ips
+    # ends with a shorter sweep
     dtype = np.float64 if precision == E.F64 else np.float32
     gs = _batch(dtype)
-    p1 = E.SolverParams(precision=precision, ls_mode=E.LS_FIXED, max_iter=K, tol_res=0.0, check_every=K + (K & 1))
-    p2 = dataclasses.replace(p1, iters_per_sweep=2)
+    ce = ips * (K // ips + 1)  # a multiple of ips past K: no stop-rule check
+    p1 = E.SolverParams(precision=precision, ls_mode=E.LS_FIXED, max_iter=K, tol_res=0.0, check_every=ce)
+    p2 = dataclasses.replace(p1, iters_per_sweep=ips)
     out = {}
     s = None
     for rows in (16, 1, 3):
@@ -61,11 +64,13 @@ def test_two_iterations_per_sweep_equal_one_iteration_per_sweep(precision, K):
             out[tag, rows, "sweeps"] = plan.query()["last_sweeps"]
             plan.close()
     ref = out["one", 16]
-    log(f"  precision={precision} K={K}: sweeps one/two {out['one', 16, 'sweeps']}/{out['two', 16, 'sweeps']}")
+    log(f"  precision={precision} ips={ips} K={K}: sweeps one/multi {out['one', 16, 'sweeps']}/"
+        f"{out['two', 16, 'sweeps']}")
     for rows in (16, 1, 3):
         emd, phi, u, info = out["two", rows]
-        # the two-iteration sweep marches even strips down and odd strips up with the
-        # same per-row arithmetic: any tiling gives its bits, which are those of the
+        # the multi-iteration sweeps form every row with the calls and operands of
+        # the one-iteration sweep (the two-iteration one marching even strips down
+        # and odd strips up): any tiling gives its bits, which are those of the
         # one-iteration sweep
         np.testing.assert_array_equal(phi, ref[1], err_msg=f"two, rows {rows}")
         np.testing.assert_array_equal(u, ref[2], err_msg=f"two, rows {rows}")
@@ -79,11 +84,14 @@ def test_two_iterations_per_sweep_equal_one_iteration_per_sweep(precision, K):
         # and the one-iteration sweep gives the same bits under every tiling
         np.testing.assert_array_equal(out["one", rows][1], ref[1])
         np.testing.assert_array_equal(out["one", rows][2], ref[2])
-    assert out["two", 16, "sweeps"] * 2 <= out["one", 16, "sweeps"] + 4
+    # about 1/ips as many sweeps (each solve rounds its sweeps up to whole chunks)
+    assert out["two", 16, "sweeps"] <= out["one", 16, "sweeps"] // ips + 4
 
 
 @pytest.mark.parametrize("tol", [0.0, 1e-4])
 def test_two_iterations_per_sweep_match_the_oracle(tol):
+    # (three iterations per sweep run in FP32 only; they are held to the one-iteration
+    # sweep bitwise above, which is held to the oracle in the parity tests)
     gs = _batch(np.float64)
     K = 300 if tol == 0.0 else 20000
     p = E.SolverParams(precision=E.F64, ls_mode=E.LS_FIXED, iters_per_sweep=2, max_iter=K, tol_res=tol,
@@ -112,7 +120,10 @@ def test_two_iterations_per_sweep_match_the_oracle(tol):
     plan.close()
 
 
-def test_resume_from_an_odd_count_with_two_iterations_per_sweep():
+@pytest.mark.parametrize("ips", [2, 3])
+def test_resume_from_an_odd_count_with_two_iterations_per_sweep(ips):
+    # 151 iterations one per sweep, then ips per sweep to 400: the first resumed sweep
+    # realigns the count, the last one ends at 400
     gs = _batch(np.float32)
     K1, K2 = 151, 400
     p1 = E.SolverParams(precision=E.F32, ls_mode=E.LS_FIXED, max_iter=K2, tol_res=0.0, check_every=K2)
@@ -123,7 +134,7 @@ def test_resume_from_an_odd_count_with_two_iterations_per_sweep():
     u = plan.empty(2)
     _, phi, u, _ = E.emd_pdhg_solve(plan, s, u=u, mass=mass)
     state = E.solver_state(plan)
-    plan.set_params(dataclasses.replace(p1, iters_per_sweep=2))
+    plan.set_params(dataclasses.replace(p1, iters_per_sweep=ips, check_every=ips * (K2 // ips + 1)))
     emd, phi, u, info = E.emd_pdhg_solve_resume(plan, s, state, u, phi, mass=mass)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(phi.cpu().numpy(), ref[1])
