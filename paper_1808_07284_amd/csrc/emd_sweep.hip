@@ -1600,8 +1600,9 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
 // three rows back, so row i + 1's s is loaded at the end of step i, into the set of
 // row i - 3 that stage 3 has just read, and first used two steps later.  A sweep of
 // one or two iterations (to realign a count, or at max_iter) runs the first stages
-// only, with the one- or two-row halo.  The same 28 bytes per cell as the
-// two-iteration sweep now carry three iterations (9.3 per iteration).
+// only, with the one- or two-row halo.  Even strips march down, odd strips up
+// (Pipe3Up).  The same 28 bytes per cell as the two-iteration sweep now carry three
+// iterations (9.3 per iteration).
 // ======================================================================================
 
 template <typename T, bool EDGE>
@@ -1727,9 +1728,121 @@ struct Pipe3 : Pipe2<T, EDGE> {
     }
 };
 
+// The upward march of the three-iteration sweep, on odd strips (as Pipe2Up for two
+// iterations): marching up, stage s forms at step i the primal update P_s of row
+// i + s (it needs the dual iterate of the row above, row i + s - 1) and A_{k+s}, D_s
+// of row i + s (the divergence needs the flux of row i + s + 1, formed one step
+// earlier).  Same calls on the same operands as the downward march, so the fields are
+// bitwise the same.  Loaded u^x, u^t, phi by (ilast - row) mod 4; s of row i - 1 is
+// loaded at the end of step i into the set of row i + 3, which stage 3 has just read.
+template <typename T, bool EDGE>
+struct Pipe3Up : Pipe3<T, EDGE> {
+    using B3 = Pipe3<T, EDGE>;
+    using B3::c;
+    using B3::LX;
+    using B3::LT;
+    using B3::LP;
+    using B3::LS;
+    using B3::P1X;
+    using B3::P1T;
+    using B3::A1;
+    using B3::D1;
+    using B3::P2X;
+    using B3::P2T;
+    using B3::A2;
+    using B3::D2;
+    using B3::P3X;
+    using B3::P3T;
+    static constexpr int V = Vec<T>::N;
+
+    __device__ explicit Pipe3Up(const TileCtx<T>& ctx) : B3(ctx) {}
+
+    // step on row i; S = (ilast - i) mod 4; K: iterations this sweep runs
+    template <int S, int K>
+    __device__ __forceinline__ void step_up(int i)
+    {
+        constexpr int C = S, U1 = (S + 3) & 3, U2 = (S + 2) & 3, U3 = (S + 1) & 3, NX = (S + 1) & 3;
+        constexpr int P = S & 1, Q = P ^ 1;  // computed rows: i + 1, i + 3 in set Q; i + 2, i + 4 in P
+        this->load_f(i - 1, LX[NX], LT[NX], LP[NX]);
+        // stage 1: P1, A_k, A_{k+1} and D1 of row i + 1
+        const int m = i + 1;
+        this->prox_row(LX[U1], LT[U1], LP[U1], LP[C], m > 0, P1X[Q], P1T[Q]);
+        const bool nxt = m + 1 < c.nr, prv = m > 0;
+        T a0[V], a1[V];
+        div_row<T, EDGE>(c, nxt, prv, LX[U1], LX[U2], LT[U1], lane_next(LT[U1][0]), LS[U1], a0);
+        div_row<T, EDGE>(c, nxt, prv, P1X[Q], P1X[P], P1T[Q], lane_next(P1T[Q][0]), LS[U1], a1);
+        this->dual_row(a1, a0, LP[U1], D1[Q]);
+#pragma unroll
+        for (int k = 0; k < V; ++k) A1[Q][k] = a1[k];
+        if constexpr (K == 1) {
+            this->store(c.uxo, this->store_off(m), P1X[Q]);
+            this->store(c.uto, this->store_off(m), P1T[Q]);
+            this->store(c.phio, this->store_off(m), D1[Q]);
+            this->sum_flux(m, P1X[Q], P1T[Q]);
+            this->sum_res(m, a1);
+        } else {
+            // stage 2: P2, A_{k+2} and D2 of row i + 2
+            const int m2 = i + 2;
+            this->prox_row(P1X[P], P1T[P], D1[P], D1[Q], m2 > 0, P2X[P], P2T[P]);
+            T a2[V];
+            div_row<T, EDGE>(c, m2 + 1 < c.nr, m2 > 0, P2X[P], P2X[Q], P2T[P], lane_next(P2T[P][0]),
+                             LS[U2], a2);
+            if constexpr (K == 2) {
+                this->store(c.uxo, this->store_off(m2), P2X[P]);
+                this->store(c.uto, this->store_off(m2), P2T[P]);
+                this->sum_flux(m2, P2X[P], P2T[P]);
+                T d2[V];
+                this->dual_row(a2, A1[P], D1[P], d2);
+                this->store(c.phio, this->store_off(m2), d2);
+                this->sum_res(m2, a2);
+            } else {
+                this->dual_row(a2, A1[P], D1[P], D2[P]);
+#pragma unroll
+                for (int k = 0; k < V; ++k) A2[P][k] = a2[k];
+                // stage 3: P3, A_{k+3} and D3 of row i + 3
+                const int m3 = i + 3;
+                this->prox_row(P2X[Q], P2T[Q], D2[Q], D2[P], m3 > 0, P3X[Q], P3T[Q]);
+                this->store(c.uxo, this->store_off(m3), P3X[Q]);
+                this->store(c.uto, this->store_off(m3), P3T[Q]);
+                this->sum_flux(m3, P3X[Q], P3T[Q]);
+                T a3[V], d3[V];
+                div_row<T, EDGE>(c, m3 + 1 < c.nr, m3 > 0, P3X[Q], P3X[P], P3T[Q], lane_next(P3T[Q][0]),
+                                 LS[U3], a3);
+                this->dual_row(a3, A2[Q], D2[Q], d3);
+                this->store(c.phio, this->store_off(m3), d3);
+                this->sum_res(m3, a3);
+            }
+        }
+        // s of row i - 1, into the set stage 3 read above (first used at step i - 2)
+        this->load_s(i - 1, LS[NX]);
+    }
+
+    // steps from the last loaded row up to (and including) row iend_up
+    template <int K>
+    __device__ __forceinline__ void run_up(int iend_up)
+    {
+        this->load_f(c.ilast, LX[0], LT[0], LP[0]);
+        this->load_s(c.ilast, LS[0]);
+        int i = c.ilast;
+        for (; i - 3 >= iend_up; i -= 4) {
+            step_up<0, K>(i);
+            step_up<1, K>(i - 1);
+            step_up<2, K>(i - 2);
+            step_up<3, K>(i - 3);
+        }
+        if (i >= iend_up) {
+            step_up<0, K>(i--);
+            if (i >= iend_up) {
+                step_up<1, K>(i--);
+                if (i >= iend_up) step_up<2, K>(i--);
+            }
+        }
+    }
+};
+
 template <typename T, bool EDGE>
 __device__ void sweep_tile3(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
-                            double* red)
+                            double* red, bool up)
 {
     constexpr int V = Vec<T>::N;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1777,13 +1890,22 @@ __device__ void sweep_tile3(const SweepArgs<T>& a, const Tile& tl, const GatherM
     c.theta = T(1.0);
     c.alpha = T(d.alpha);
     c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
-    Pipe3<T, EDGE> P(c);
-    // the last own row's D_K comes from the step K - 1 rows below it (rows past the
-    // grid are virtual: nothing is loaded there and their weights are zero)
-    P.iend = c.rend + d.steps - 1;
-    if (d.steps == 3) P.template run<3>();
-    else if (d.steps == 2) P.template run<2>();
-    else P.template run<1>();
+    // one pipeline object for both directions (a run-time, wave-uniform branch, as in
+    // the two-iteration sweep)
+    Pipe3Up<T, EDGE> P(c);
+    if (up) {
+        // the first own row's outputs come from the step K rows above it
+        if (d.steps == 3) P.template run_up<3>(c.r0 - 3);
+        else if (d.steps == 2) P.template run_up<2>(c.r0 - 2);
+        else P.template run_up<1>(c.r0 - 1);
+    } else {
+        // the last own row's D_K comes from the step K - 1 rows below it (rows past
+        // the grid are virtual: nothing is loaded there and their weights are zero)
+        P.iend = c.rend + d.steps - 1;
+        if (d.steps == 3) P.template run<3>();
+        else if (d.steps == 2) P.template run<2>();
+        else P.template run<1>();
+    }
     double r[NPART];
 #pragma unroll
     for (int m = 0; m < NPART; ++m) r[m] = 0.0;
@@ -1841,8 +1963,10 @@ __global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
     }
     const int pb = parity;
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
-    if (edge) sweep_tile3<T, true>(a, tl, gm, parity, pb, w, xred);
-    else sweep_tile3<T, false>(a, tl, gm, parity, pb, w, xred);
+    // odd strips march up
+    const bool up = ((tl.r0 / gm.rows) & 1) != 0;
+    if (edge) sweep_tile3<T, true>(a, tl, gm, parity, pb, w, xred, up);
+    else sweep_tile3<T, false>(a, tl, gm, parity, pb, w, xred, up);
 }
 
 template <typename T>
