@@ -39,9 +39,9 @@ BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi,
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest, per kernel; the traffic figure is null for any other
 # source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "9c62395ed5af030b",
-                    "ratio": {"k_sweep<float, false>": 1.0732, "k_sweep2<float>": 1.0624,
-                              "k_sweep3<float>": 1.1468}}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "07502a5718993832",
+                    "ratio": {"k_sweep<float, false>": 1.0725, "k_sweep2<float>": 1.0635,
+                              "k_sweep3<float>": 1.0440}}
 
 
 def sweep_source_digest():
