@@ -144,20 +144,28 @@ def test_resume_from_an_odd_count_with_two_iterations_per_sweep(ips):
 
 
 def test_two_iterations_per_sweep_on_the_benchmark_batch():
-    # full size, default tiling: 40 iterations of the 64-gather batch, bitwise the
-    # fields of the one-iteration sweep
+    # full size: 40 iterations of the 64-gather batch, bitwise the fields of the
+    # one-iteration sweep, two per sweep on the default tiles and three per sweep on
+    # the benchmark's 24-row tiles (40 = 13 x 3 + 1: the last sweep runs one)
     gs = config3_batch()
-    p1 = E.SolverParams(precision=E.F32, ls_mode=E.LS_FIXED, max_iter=40, tol_res=0.0, check_every=40)
+    p1 = E.SolverParams(precision=E.F32, ls_mode=E.LS_FIXED, max_iter=40, tol_res=0.0, check_every=42)
     res = []
-    for p in (p1, dataclasses.replace(p1, iters_per_sweep=2)):
+    s = None
+    for p, rows in ((p1, 0), (dataclasses.replace(p1, iters_per_sweep=2), 0),
+                    (dataclasses.replace(p1, iters_per_sweep=3), 24)):
         plan, pcal, pobs, desc = make_plan(gs, p)
-        s, mass = E.emd_decompose(plan, pcal, pobs)
+        if rows:
+            plan.set_tiling(rows)
+        if s is None:
+            # one source for every tiling (the decompose's FP64 sums are taken per tile)
+            s, mass = E.emd_decompose(plan, pcal, pobs)
         res.append(_run(plan, s, mass))
         plan.close()
-        del pcal, pobs, s
-    np.testing.assert_array_equal(res[1][1], res[0][1])
-    np.testing.assert_array_equal(res[1][2], res[0][2])
-    np.testing.assert_allclose(res[1][0], res[0][0], rtol=1e-6)
+        del pcal, pobs
+    for r in res[1:]:
+        np.testing.assert_array_equal(r[1], res[0][1])
+        np.testing.assert_array_equal(r[2], res[0][2])
+        np.testing.assert_allclose(r[0], res[0][0], rtol=1e-6)
 
 
 def test_two_iterations_per_sweep_rejected_with_a_linesearch():
