@@ -1444,21 +1444,25 @@ struct Pipe2Up : Pipe2<T, EDGE> {
     }
 };
 
-template <typename T, bool EDGE>
-__device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
-                            double* red, bool up)
+// The view of one tile for a fixed-step sweep of up to K iterations: the strip's rows
+// with K halo rows above and below it, the lane's samples, and the buffer descriptors
+// of the fields it reads (buffer parity pb) and writes.  The steps are set once the
+// gather's decision is taken (set_steps).
+template <typename T>
+__device__ __forceinline__ TileCtx<T> fixed_tile_ctx(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm,
+                                                     int pb, int K)
 {
     constexpr int V = Vec<T>::N;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int q = p ^ 1, qb = pb ^ 1;
+    const int qb = pb ^ 1;
     TileCtx<T> c;
     c.nr = gm.nr;
     c.ld = gm.ld;
     const int nt = gm.nt;
     c.r0 = tl.r0;
     c.rend = min(tl.r0 + gm.rows, gm.nr);
-    c.ibeg = max(tl.r0 - 2, 0);
-    c.ilast = min(c.rend + 1, gm.nr - 1);  // last row loaded (two below the strip)
+    c.ibeg = max(tl.r0 - K, 0);
+    c.ilast = min(c.rend + K - 1, gm.nr - 1);
     const int j0 = tl.c0 - V + V * lane;
     const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
     c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
@@ -1487,15 +1491,44 @@ __device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherM
     c.phio = rs(a.phi[qb]);
     c.ri = c.si;
     c.ro = c.phio;
+    return c;
+}
 
-    const Decision2 d = decide_fixedk<T, 2>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
-    if (d.steps == 0) return;
+template <typename T>
+__device__ __forceinline__ void set_steps(TileCtx<T>& c, const SweepArgs<T>& a, const Decision2& d)
+{
     c.beta = T(d.beta);
     c.theta = T(1.0);
     c.alpha = T(d.alpha);
     c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
-    double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
-    double aa, l1, l2;
+}
+
+// A gather's stop-rule sums of this tile, written to its partial-sum slot.
+template <typename T>
+__device__ __forceinline__ void write_fixed_sums(const SweepArgs<T>& a, const Tile& tl, int q, double aa, double l1,
+                                                 double l2)
+{
+    double r[NPART];
+#pragma unroll
+    for (int m = 0; m < NPART; ++m) r[m] = 0.0;
+    r[0] = wave_sum(aa);
+    r[6] = wave_sum(l1);
+    r[7] = wave_sum(l2);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
+#pragma unroll
+        for (int m = 0; m < NPART; ++m) dst[m] = r[m];
+    }
+}
+
+template <typename T, bool EDGE>
+__device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
+                            double* red, bool up)
+{
+    TileCtx<T> c = fixed_tile_ctx<T>(a, tl, gm, pb, 2);
+    const Decision2 d = decide_fixedk<T, 2>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
+    if (d.steps == 0) return;
+    set_steps<T>(c, a, d);
     // one pipeline object for both directions: with the direction a run-time (wave-
     // uniform) branch the kernel keeps the register count of one direction (118
     // VGPRs in FP32, four waves per SIMD) where two instantiations took 140
@@ -1505,84 +1538,16 @@ __device__ void sweep_tile2(const SweepArgs<T>& a, const Tile& tl, const GatherM
         // rows above it
         if (d.steps == 2) P.template run_up<true>(c.r0 - 2);
         else P.template run_up<false>(c.r0 - 1);
-        aa = P.aa;
-        l1 = P.l1;
-        l2 = P.l2;
     } else {
-        if (d.steps == 2) {
-            // the last own row's D2 needs the step two rows below it (rows past the
-            // grid are virtual: nothing is loaded there and their weights are zero)
-            P.iend = c.rend + 1;
-            P.template run<true>();
-        } else {
-            P.iend = c.rend;
-            P.template run<false>();
-        }
-        aa = P.aa;
-        l1 = P.l1;
-        l2 = P.l2;
+        // the last own row's D_K comes from the step K - 1 rows below it (rows past
+        // the grid are virtual: nothing is loaded there and their weights are zero)
+        P.iend = c.rend + d.steps - 1;
+        if (d.steps == 2) P.template run<true>();
+        else P.template run<false>();
     }
-    double r[NPART];
-#pragma unroll
-    for (int m = 0; m < NPART; ++m) r[m] = 0.0;
-    r[0] = wave_sum(aa);
-    r[6] = wave_sum(l1);
-    r[7] = wave_sum(l2);
-    if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < NPART; ++m) dst[m] = r[m];
-    }
+    write_fixed_sums<T>(a, tl, p ^ 1, P.aa, P.l1, P.l2);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
-{
-    constexpr int V = Vec<T>::N;
-    constexpr int WPB = 256 / WAVE;
-    __shared__ double red[WPB * NPART];
-    const int w = uniform((int)threadIdx.x / WAVE);
-    const int first = uniform(xcd_logical_block() * WPB);
-    const int tid = first + w;
-    if (tid >= a.ntiles) return;
-    // the four waves of a block on one running gather share its decision sums (as in
-    // k_sweep; every wave of such a block reaches the one barrier)
-    int gb = -1;
-    bool split = first + WPB <= a.ntiles;
-    for (int k = 0; k < WPB && split; ++k) {
-        const int gk = uniform(a.tiles[first + k].g);
-        if (gk < 0) continue;
-        if (gb < 0) gb = gk;
-        else if (gk != gb) split = false;
-    }
-    if (gb < 0) split = false;
-    if (split) {
-        const GState* sb = a.gst[parity] + gb;
-        split = uniform(sb->status) == ST_RUNNING && uniform(sb->started) != 0;
-    }
-    const Tile tl = a.tiles[tid];
-    const int g = uniform(tl.g);
-    if (g < 0) {
-        if (split) {
-            const GatherMeta mb = a.meta[gb];
-            double s[NPART];
-            decision_sums<NPART>(a.part[parity] + (int64_t)mb.tile_base * NPART, mb.ntiles, w, red, s);
-        }
-        return;
-    }
-    double* const xred = split ? red : nullptr;
-    const GatherMeta gm = a.meta[g];
-    const GState* gs = a.gst[parity] + g;
-    if (gs->status != ST_RUNNING) {
-        if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0) a.gst[parity ^ 1][g] = *gs;
-        return;
-    }
-    const int pb = parity;
-    const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
-    // odd strips march up
-    const bool up = ((tl.r0 / gm.rows) & 1) != 0;
-    if (edge) sweep_tile2<T, true>(a, tl, gm, parity, pb, w, xred, up);
-    else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred, up);
-}
 
 // ======================================================================================
 // Plain PDHG with fixed steps, three iterations per HBM pass (iters_per_sweep = 3): the
@@ -1844,52 +1809,10 @@ template <typename T, bool EDGE>
 __device__ void sweep_tile3(const SweepArgs<T>& a, const Tile& tl, const GatherMeta& gm, int p, int pb, int w,
                             double* red, bool up)
 {
-    constexpr int V = Vec<T>::N;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int q = p ^ 1, qb = pb ^ 1;
+    TileCtx<T> c = fixed_tile_ctx<T>(a, tl, gm, pb, 3);
     const Decision2 d = decide_fixedk<T, 3>(a, p, tl.g, gm, tl.slot == gm.tile_base, pb, w, red);
     if (d.steps == 0) return;
-    TileCtx<T> c;
-    c.nr = gm.nr;
-    c.ld = gm.ld;
-    const int nt = gm.nt;
-    c.r0 = tl.r0;
-    c.rend = min(tl.r0 + gm.rows, gm.nr);
-    // a sweep of K iterations reads K rows above and below the strip
-    c.ibeg = max(tl.r0 - d.steps, 0);
-    c.ilast = min(c.rend + d.steps - 1, gm.nr - 1);
-    const int j0 = tl.c0 - V + V * lane;
-    const bool lane_load = (lane <= HALO_LANE_R) && (j0 >= 0) && (j0 < nt);
-    c.lane_out = (lane >= 1) && (lane <= OUT_LANES) && lane_load;
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-        const int j = j0 + k;
-        c.inb[k] = (j >= 0) && (j < nt);
-        c.jgt0[k] = j > 0;
-        c.jlt[k] = j + 1 < nt;
-    }
-    c.idx = T(1.0 / gm.dx);
-    c.idt = T(1.0 / gm.dt);
-    c.row_bytes = (uint32_t)(gm.ld * sizeof(T));
-    c.vb_ld = lane_load ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
-    c.vb_st = c.lane_out ? (uint32_t)(j0 * (int)sizeof(T)) : OOB;
-    const int bytes = (int)((int64_t)gm.nr * gm.ld * sizeof(T));
-    auto rs = [&](const T* f) {
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f + gm.poff), 0, bytes, 0x00020000);
-    };
-    c.uxi = rs(a.ux[pb]);
-    c.uti = rs(a.ut[pb]);
-    c.phi_i = rs(a.phi[pb]);
-    c.si = rs(a.s);
-    c.uxo = rs(a.ux[qb]);
-    c.uto = rs(a.ut[qb]);
-    c.phio = rs(a.phi[qb]);
-    c.ri = c.si;
-    c.ro = c.phio;
-    c.beta = T(d.beta);
-    c.theta = T(1.0);
-    c.alpha = T(d.alpha);
-    c.inv = T(1.0 / (1.0 + a.sc.eps * d.alpha));
+    set_steps<T>(c, a, d);
     // one pipeline object for both directions (a run-time, wave-uniform branch, as in
     // the two-iteration sweep)
     Pipe3Up<T, EDGE> P(c);
@@ -1906,31 +1829,22 @@ __device__ void sweep_tile3(const SweepArgs<T>& a, const Tile& tl, const GatherM
         else if (d.steps == 2) P.template run<2>();
         else P.template run<1>();
     }
-    double r[NPART];
-#pragma unroll
-    for (int m = 0; m < NPART; ++m) r[m] = 0.0;
-    r[0] = wave_sum(P.aa);
-    r[6] = wave_sum(P.l1);
-    r[7] = wave_sum(P.l2);
-    if (lane == 0) {
-        double* __restrict__ dst = a.part[q] + (int64_t)tl.slot * NPART;
-#pragma unroll
-        for (int m = 0; m < NPART; ++m) dst[m] = r[m];
-    }
+    write_fixed_sums<T>(a, tl, p ^ 1, P.aa, P.l1, P.l2);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
+// The fixed-step sweep of K (2 or 3) iterations per launch over one tile table.  The
+// four waves of a block on one running gather share its decision sums (as in k_sweep;
+// every wave of such a block reaches the one barrier).  red: the block's exchange
+// buffer (LDS, 4 * NPART doubles).
+template <typename T, int K>
+__device__ __forceinline__ void fixed_sweep(const SweepArgs<T>& a, int parity, double* red)
 {
     constexpr int V = Vec<T>::N;
     constexpr int WPB = 256 / WAVE;
-    __shared__ double red[WPB * NPART];
     const int w = uniform((int)threadIdx.x / WAVE);
     const int first = uniform(xcd_logical_block() * WPB);
     const int tid = first + w;
     if (tid >= a.ntiles) return;
-    // the four waves of a block on one running gather share its decision sums (as in
-    // k_sweep; every wave of such a block reaches the one barrier)
     int gb = -1;
     bool split = first + WPB <= a.ntiles;
     for (int k = 0; k < WPB && split; ++k) {
@@ -1947,6 +1861,7 @@ __global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
     const Tile tl = a.tiles[tid];
     const int g = uniform(tl.g);
     if (g < 0) {
+        // padding entry: only its quarter of the block gather's decision sums
         if (split) {
             const GatherMeta mb = a.meta[gb];
             double s[NPART];
@@ -1958,6 +1873,7 @@ __global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
     const GatherMeta gm = a.meta[g];
     const GState* gs = a.gst[parity] + g;
     if (gs->status != ST_RUNNING) {
+        // finished gather: only carry its state to the other parity
         if (tl.slot == gm.tile_base && (threadIdx.x & (WAVE - 1)) == 0) a.gst[parity ^ 1][g] = *gs;
         return;
     }
@@ -1965,8 +1881,27 @@ __global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
     const bool edge = (tl.c0 - V < 1) || (tl.c0 + HALO_LANE_R * V > gm.nt - 1);
     // odd strips march up
     const bool up = ((tl.r0 / gm.rows) & 1) != 0;
-    if (edge) sweep_tile3<T, true>(a, tl, gm, parity, pb, w, xred, up);
-    else sweep_tile3<T, false>(a, tl, gm, parity, pb, w, xred, up);
+    if constexpr (K == 2) {
+        if (edge) sweep_tile2<T, true>(a, tl, gm, parity, pb, w, xred, up);
+        else sweep_tile2<T, false>(a, tl, gm, parity, pb, w, xred, up);
+    } else {
+        if (edge) sweep_tile3<T, true>(a, tl, gm, parity, pb, w, xred, up);
+        else sweep_tile3<T, false>(a, tl, gm, parity, pb, w, xred, up);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep2(SweepArgs<T> a, int parity)
+{
+    __shared__ double red[(256 / WAVE) * NPART];
+    fixed_sweep<T, 2>(a, parity, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep3(SweepArgs<T> a, int parity)
+{
+    __shared__ double red[(256 / WAVE) * NPART];
+    fixed_sweep<T, 3>(a, parity, red);
 }
 
 template <typename T>
