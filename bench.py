@@ -39,9 +39,9 @@ BYTES_PER_CELL_ITER = {"f32": 36, "f64": 72}  # read u, phi, s, R; write u, phi,
 # FETCH_SIZE / WRITE_SIZE profiler runs (scaled by a plain copy's readings) of the
 # sweep source with this digest, per kernel; the traffic figure is null for any other
 # source.
-MEASURED_TRAFFIC = {"sweep_source_sha256_16": "07502a5718993832",
-                    "ratio": {"k_sweep<float, false>": 1.0725, "k_sweep2<float>": 1.0635,
-                              "k_sweep3<float>": 1.0440}}
+MEASURED_TRAFFIC = {"sweep_source_sha256_16": "4b79b79f83f54e78",
+                    "ratio": {"k_sweep<float, false>": 1.0734, "k_sweep2<float>": 1.0630,
+                              "k_sweep3<float>": 1.0420}}
 
 
 def sweep_source_digest():
