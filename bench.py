@@ -392,6 +392,34 @@ def main():
     extra["one_pass_kernels"] = {
         "decompose": {"ms": round(t_dec, 3), "GB/s_at_12B_per_cell": round(12 * cells / t_dec / 1e6, 1)},
         "adjoint": {"ms": round(t_adj, 3), "GB/s_at_8B_per_cell": round(8 * cells / t_adj / 1e6, 1)}}
+    if mg is not None:
+        # the grid transfers between the fine grid and its first coarse level: the
+        # restriction of one field (reads the fine field, writes the coarse one: 4 B per
+        # fine and per coarse cell) and the prolongation of u and phi (12 B per coarse
+        # and per fine cell)
+        cp, fr, ft = mg.levels[0]
+        nc = cp.batch_len
+        xr = cp.empty()
+        uc, pc = cp.empty(2).normal_(), cp.empty().normal_()
+        uf, pf = plan.empty(2), plan.empty()
+        evt = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        E.restrict(plan, cp, fr, ft, pcal, out=xr)
+        E.prolong(cp, plan, fr, ft, uc, pc, u_out=uf, phi_out=pf)
+        evt[0].record(stream)
+        for _ in range(reps):
+            E.restrict(plan, cp, fr, ft, pcal, out=xr)
+        evt[1].record(stream)
+        for _ in range(reps):
+            E.prolong(cp, plan, fr, ft, uc, pc, u_out=uf, phi_out=pf)
+        evt[2].record(stream)
+        torch.cuda.synchronize()
+        t_res = evt[0].elapsed_time(evt[1]) / reps
+        t_pro = evt[1].elapsed_time(evt[2]) / reps
+        extra["one_pass_kernels"]["restrict_fine_level"] = {
+            "ms": round(t_res, 3), "GB/s_at_4B_per_fine_and_coarse_cell": round(4 * (cells + nc) / t_res / 1e6, 1)}
+        extra["one_pass_kernels"]["prolong_fine_level"] = {
+            "ms": round(t_pro, 3), "GB/s_at_12B_per_fine_and_coarse_cell": round(12 * (cells + nc) / t_pro / 1e6, 1)}
+        del xr, uc, pc, uf, pf
     roofline["measured_copy_GBs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
     log(f"decompose {t_dec:.3f} ms, adjoint {t_adj:.3f} ms, 1 GiB copy {copy_gbs:.0f} GB/s")

@@ -3,10 +3,13 @@
 // batch into the padded solver state and back, per-gather start-up and results,
 // and the adjoint source (Section 2.3).
 //
-// All passes use the sweep tile table: a wavefront covers `rows` receiver rows by
-// 56 * V time samples of one gather (lanes 1..56, V samples each), so per-gather
-// sums are built from per-tile partials (one slot per tile, contiguous per gather)
-// reduced in a fixed order (deterministic).
+// All passes use the sweep tile table, one wavefront per entry, so per-gather sums
+// are built from per-tile partials (one slot per tile, contiguous per gather) reduced
+// in a fixed order (deterministic).  Passes between the padded state and the caller's
+// layout cover the tile itself (`rows` receiver rows by 56 * V time samples, lanes
+// 1..56 with V samples each); passes that touch only the caller's layout (decompose,
+// adjoint, least squares) walk a contiguous chunk of the gather's elements per slot,
+// consecutive lanes on consecutive elements.
 #include "emd_internal.h"
 #include "emd_launch.h"
 
@@ -50,6 +53,31 @@ __device__ __forceinline__ void write_record(double* part, int slot, const doubl
     if (lane == 0) {
 #pragma unroll
         for (int m = 0; m < NPART; ++m) part[(int64_t)slot * NPART + m] = r[m];
+    }
+}
+
+// The elements whose sums go to a tile's slot, for the passes over the caller's
+// layout: gather g's nr * nt elements (row-major) cut into ntiles contiguous chunks,
+// chunk c for slot tile_base + c.  Offsets are relative to the gather's first element.
+__device__ __forceinline__ void slot_chunk(const TileView& tv, const GatherMeta& gm, int64_t& lo, int64_t& hi)
+{
+    const int64_t n = (int64_t)gm.nr * gm.nt;
+    const int64_t per = (n + gm.ntiles - 1) / gm.ntiles;
+    lo = min((int64_t)(tv.slot - gm.tile_base) * per, n);
+    hi = min(lo + per, n);
+}
+
+// A wave takes kUnroll strided elements per step (e, e + 64, ...), all loads of a
+// step issued before any is used; elements at or past hi read as zero.
+constexpr int kUnroll = 4;
+
+template <typename T>
+__device__ __forceinline__ void load_step(const T* __restrict__ p, int64_t e, int64_t hi, double (&x)[kUnroll])
+{
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = e + (int64_t)u * WAVE;
+        x[u] = k < hi ? double(p[k]) : 0.0;
     }
 }
 
@@ -296,25 +324,27 @@ __device__ __forceinline__ double gpart(double pc, double po) { return fmax(po, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_decomp_sums(AuxArgs<T> a)
 {
-    constexpr int V = Vec<T>::N;
     GatherMeta gm;
     bool ok;
     const TileView tv = tile_view(a, gm, ok);
     if (!ok) return;
+    int64_t lo, hi;
+    slot_chunk(tv, gm, lo, hi);
+    const T* __restrict__ pcal = a.pcal + gm.uoff;
+    const T* __restrict__ pobs = a.pobs + gm.uoff;
     double acc[NPART];
 #pragma unroll
     for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
-    if (tv.active) {
-        for (int i = tv.r0; i < tv.rend; ++i) {
-            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+    for (int64_t e = lo + tv.lane; e < hi; e += kUnroll * WAVE) {
+        double pc[kUnroll], po[kUnroll];
+        load_step(pcal, e, hi, pc);
+        load_step(pobs, e, hi, po);
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (tv.j0 + k >= gm.nt) break;
-                const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
-                acc[0] += fpart(pc, po);
-                acc[1] += gpart(pc, po);
-                acc[2] += pc - po;
-            }
+        for (int u = 0; u < kUnroll; ++u) {
+            if (e + (int64_t)u * WAVE >= hi) break;
+            acc[0] += fpart(pc[u], po[u]);
+            acc[1] += gpart(pc[u], po[u]);
+            acc[2] += pc[u] - po[u];
         }
     }
     write_record(a.part, tv.slot, acc);
@@ -337,27 +367,35 @@ __global__ __launch_bounds__(64) void k_decomp_mass(AuxArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(256) void k_decomp_source(AuxArgs<T> a)
 {
-    constexpr int V = Vec<T>::N;
     GatherMeta gm;
     bool ok;
     const TileView tv = tile_view(a, gm, ok);
-    if (!ok || !tv.active) return;
+    if (!ok) return;
+    int64_t lo, hi;
+    slot_chunk(tv, gm, lo, hi);
+    const T* __restrict__ pcal = a.pcal + gm.uoff;
+    const T* __restrict__ pobs = a.pobs + gm.uoff;
+    T* __restrict__ s_out = a.s_out + gm.uoff;
+    T* __restrict__ f_out = a.f_out ? a.f_out + gm.uoff : nullptr;
+    T* __restrict__ g_out = a.g_out ? a.g_out + gm.uoff : nullptr;
     const double Mf = a.mass_out[3 * tv.g], Mg = a.mass_out[3 * tv.g + 1];
     const double mean = a.mass_out[3 * tv.g + 2];
-    for (int i = tv.r0; i < tv.rend; ++i) {
-        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+    for (int64_t e = lo + tv.lane; e < hi; e += kUnroll * WAVE) {
+        double pc[kUnroll], po[kUnroll];
+        load_step(pcal, e, hi, pc);
+        load_step(pobs, e, hi, po);
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            if (tv.j0 + k >= gm.nt) break;
-            const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
-            const double f = fpart(pc, po), g = gpart(pc, po);
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t k = e + (int64_t)u * WAVE;
+            if (k >= hi) break;
+            const double f = fpart(pc[u], po[u]), g = gpart(pc[u], po[u]);
             double s;
-            if (a.mass_mode == MASS_BALANCE) s = (pc - po) - mean;
+            if (a.mass_mode == MASS_BALANCE) s = (pc[u] - po[u]) - mean;
             else if (a.mass_mode == MASS_UNIT) s = (Mf > 0.0 ? f / Mf : 0.0) - (Mg > 0.0 ? g / Mg : 0.0);
-            else s = pc - po;
-            a.s_out[ur + k] = T(s);
-            if (a.f_out) a.f_out[ur + k] = T(f);
-            if (a.g_out) a.g_out[ur + k] = T(g);
+            else s = pc[u] - po[u];
+            s_out[k] = T(s);
+            if (f_out) f_out[k] = T(f);
+            if (g_out) g_out[k] = T(g);
         }
     }
 }
@@ -368,30 +406,36 @@ __global__ __launch_bounds__(256) void k_decomp_source(AuxArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_sums(AuxArgs<T> a)
 {
-    constexpr int V = Vec<T>::N;
     GatherMeta gm;
     bool ok;
     const TileView tv = tile_view(a, gm, ok);
     if (!ok) return;
+    int64_t lo, hi;
+    slot_chunk(tv, gm, lo, hi);
+    const T* __restrict__ phi = a.phi_user + gm.uoff;
+    const bool unit = a.mass_mode == MASS_UNIT;
+    const T* __restrict__ pcal = unit ? a.pcal + gm.uoff : nullptr;
+    const T* __restrict__ pobs = unit ? a.pobs + gm.uoff : nullptr;
     double acc[NPART];
 #pragma unroll
     for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
-    if (tv.active) {
-        for (int i = tv.r0; i < tv.rend; ++i) {
-            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+    for (int64_t e = lo + tv.lane; e < hi; e += kUnroll * WAVE) {
+        double ph[kUnroll], pc[kUnroll], po[kUnroll];
+        load_step(phi, e, hi, ph);
+        if (unit) {
+            load_step(pcal, e, hi, pc);
+            load_step(pobs, e, hi, po);
+        }
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (tv.j0 + k >= gm.nt) break;
-                const double ph = double(a.phi_user[ur + k]);
-                acc[0] += ph;
-                if (a.mass_mode == MASS_UNIT) {
-                    const double pc = double(a.pcal[ur + k]), po = double(a.pobs[ur + k]);
-                    const double f = fpart(pc, po), g = gpart(pc, po);
-                    acc[1] += ph * f;
-                    acc[2] += ph * g;
-                    acc[3] += f;
-                    acc[4] += g;
-                }
+        for (int u = 0; u < kUnroll; ++u) {
+            if (e + (int64_t)u * WAVE >= hi) break;
+            acc[0] += ph[u];
+            if (unit) {
+                const double f = fpart(pc[u], po[u]), g = gpart(pc[u], po[u]);
+                acc[1] += ph[u] * f;
+                acc[2] += ph[u] * g;
+                acc[3] += f;
+                acc[4] += g;
             }
         }
     }
@@ -425,30 +469,37 @@ __global__ __launch_bounds__(64) void k_adj_scalars(AuxArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_apply(AuxArgs<T> a)
 {
-    constexpr int V = Vec<T>::N;
     GatherMeta gm;
     bool ok;
     const TileView tv = tile_view(a, gm, ok);
-    if (!ok || !tv.active) return;
+    if (!ok) return;
+    int64_t lo, hi;
+    slot_chunk(tv, gm, lo, hi);
+    const T* __restrict__ phi = a.phi_user + gm.uoff;
+    const bool unit = a.mass_mode == MASS_UNIT;
+    const T* __restrict__ pcal = unit ? a.pcal + gm.uoff : nullptr;
+    T* __restrict__ psi = a.psi_out + gm.uoff;
     const double scale = a.adj[4 * tv.g], c1 = a.adj[4 * tv.g + 1], c2 = a.adj[4 * tv.g + 2];
     const double Mf = a.mass ? a.mass[3 * tv.g] : 0.0, Mg = a.mass ? a.mass[3 * tv.g + 1] : 0.0;
-    for (int i = tv.r0; i < tv.rend; ++i) {
-        const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+    for (int64_t e = lo + tv.lane; e < hi; e += kUnroll * WAVE) {
+        double ph[kUnroll], pc[kUnroll];
+        load_step(phi, e, hi, ph);
+        if (unit) load_step(pcal, e, hi, pc);
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            if (tv.j0 + k >= gm.nt) break;
-            const double ph = double(a.phi_user[ur + k]);
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t k = e + (int64_t)u * WAVE;
+            if (k >= hi) break;
             double v;
             if (a.mass_mode == MASS_BALANCE) {
-                v = scale * (ph - c1);
-            } else if (a.mass_mode == MASS_UNIT) {
-                const double h = double(a.pcal[ur + k]) > 0.0 ? 1.0 : 0.0;
-                v = scale * ((Mf > 0.0 ? h * (ph - c1) / Mf : 0.0) +
-                             (Mg > 0.0 ? (1.0 - h) * (ph - c2) / Mg : 0.0));
+                v = scale * (ph[u] - c1);
+            } else if (unit) {
+                const double h = pc[u] > 0.0 ? 1.0 : 0.0;
+                v = scale * ((Mf > 0.0 ? h * (ph[u] - c1) / Mf : 0.0) +
+                             (Mg > 0.0 ? (1.0 - h) * (ph[u] - c2) / Mg : 0.0));
             } else {
-                v = scale * ph;
+                v = scale * ph[u];
             }
-            a.psi_out[ur + k] = T(v);
+            psi[k] = T(v);
         }
     }
 }
@@ -459,25 +510,30 @@ __global__ __launch_bounds__(256) void k_adj_apply(AuxArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(256) void k_lsd_apply(AuxArgs<T> a)
 {
-    constexpr int V = Vec<T>::N;
     GatherMeta gm;
     bool ok;
     const TileView tv = tile_view(a, gm, ok);
     if (!ok) return;
+    int64_t lo, hi;
+    slot_chunk(tv, gm, lo, hi);
+    const T* __restrict__ pcal = a.pcal + gm.uoff;
+    const T* __restrict__ pobs = a.pobs + gm.uoff;
+    T* __restrict__ psi = a.psi_out ? a.psi_out + gm.uoff : nullptr;
+    const double scale = gm.cm * (a.gbar ? a.gbar[tv.g] : 1.0);
     double acc[NPART];
 #pragma unroll
     for (int m = 0; m < NPART; ++m) acc[m] = 0.0;
-    if (tv.active) {
-        const double scale = gm.cm * (a.gbar ? a.gbar[tv.g] : 1.0);
-        for (int i = tv.r0; i < tv.rend; ++i) {
-            const int64_t ur = gm.uoff + (int64_t)i * gm.nt + tv.j0;
+    for (int64_t e = lo + tv.lane; e < hi; e += kUnroll * WAVE) {
+        double pc[kUnroll], po[kUnroll];
+        load_step(pcal, e, hi, pc);
+        load_step(pobs, e, hi, po);
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (tv.j0 + k >= gm.nt) break;
-                const double d = double(a.pcal[ur + k]) - double(a.pobs[ur + k]);
-                acc[0] = fma(d, d, acc[0]);
-                if (a.psi_out) a.psi_out[ur + k] = T(scale * d);
-            }
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t k = e + (int64_t)u * WAVE;
+            if (k >= hi) break;
+            const double d = pc[u] - po[u];
+            acc[0] = fma(d, d, acc[0]);
+            if (psi) psi[k] = T(scale * d);
         }
     }
     write_record(a.part, tv.slot, acc);
@@ -554,39 +610,80 @@ __device__ __forceinline__ AxisW axis_w(int i, int f, int n, bool edge)
     return w;
 }
 
-template <typename T>
-__device__ __forceinline__ double csample(const T* v, const GatherMeta& c, int a, int b)
+// The four coarse samples a bilinear weight pair reads (k < 0 stands for a zero
+// sample).  Every load is made, at the gather's first element for a zero sample,
+// and the zeros are chosen afterwards, so that all loads of a fine sample are in
+// flight together instead of each behind a branch and a wait.
+__device__ __forceinline__ int64_t cidx(const GatherMeta& c, int a, int b)
 {
-    return (a < 0 || b < 0) ? 0.0 : double(v[c.uoff + (int64_t)a * c.nt + b]);
+    return (a < 0 || b < 0) ? c.uoff : c.uoff + (int64_t)a * c.nt + b;
 }
 
 template <typename T>
-__device__ __forceinline__ double blend(const T* v, const GatherMeta& c, const AxisW& r, const AxisW& t)
+__device__ __forceinline__ void load_quad(const T* v, const GatherMeta& c, const AxisW& r, const AxisW& t, T (&q)[4])
 {
-    return r.w0 * t.w0 * csample(v, c, r.k0, t.k0) + r.w0 * t.w1 * csample(v, c, r.k0, t.k1) +
-           r.w1 * t.w0 * csample(v, c, r.k1, t.k0) + r.w1 * t.w1 * csample(v, c, r.k1, t.k1);
+    q[0] = v[cidx(c, r.k0, t.k0)];
+    q[1] = v[cidx(c, r.k0, t.k1)];
+    q[2] = v[cidx(c, r.k1, t.k0)];
+    q[3] = v[cidx(c, r.k1, t.k1)];
+}
+
+template <typename T>
+__device__ __forceinline__ double cval(T x, int a, int b)
+{
+    return (a < 0 || b < 0) ? 0.0 : double(x);
+}
+
+template <typename T>
+__device__ __forceinline__ double blend(const T (&q)[4], const AxisW& r, const AxisW& t)
+{
+    return r.w0 * t.w0 * cval(q[0], r.k0, t.k0) + r.w0 * t.w1 * cval(q[1], r.k0, t.k1) +
+           r.w1 * t.w0 * cval(q[2], r.k1, t.k0) + r.w1 * t.w1 * cval(q[3], r.k1, t.k1);
 }
 
 // Prolongation: bilinear interpolation of the coarse u^x (receiver edges, time
 // centres), u^t (time edges, receiver centres) and phi (centres) onto the fine
-// grid.  A block walks fine rows (the receiver weights are the row's), its threads
-// the samples of a row.
-template <typename T>
+// grid.  The fine grid is cut into blocks of kProlongRows rows by 256 samples; a
+// thread block takes them in turn, computes the rows' weights once into LDS, and each
+// thread the weights of its sample once, then walks the rows.
+constexpr int kProlongRows = 16;
+
+template <typename T, bool HAS_U, bool HAS_PHI>
 __global__ __launch_bounds__(256) void k_prolong(XferArgs<T> a)
 {
+    __shared__ AxisW rw[2][kProlongRows];  // [0]: cell centres, [1]: edges
     const int g = blockIdx.y;
     const GatherMeta f = a.meta_f[g], c = a.meta_c[g];
-    for (int i = blockIdx.x; i < f.nr; i += gridDim.x) {
-        const AxisW rc = axis_w(i, a.fr, c.nr, false), re = axis_w(i, a.fr, c.nr, true);
-        const int64_t orow = f.uoff + (int64_t)i * f.nt;
-        for (int j = threadIdx.x; j < f.nt; j += blockDim.x) {
-            const AxisW tc = axis_w(j, a.ft, c.nt, false), te = axis_w(j, a.ft, c.nt, true);
-            const int64_t o = orow + j;
-            if (a.u_f) {
-                a.u_f[o] = T(blend(a.u_c, c, re, tc));
-                a.u_f[a.len_f + o] = T(blend(a.u_c + a.len_c, c, rc, te));
+    const int strips = (f.nt + 255) / 256;
+    const int pieces = strips * ((f.nr + kProlongRows - 1) / kProlongRows);
+    for (int p = blockIdx.x; p < pieces; p += gridDim.x) {
+        const int i0 = (p / strips) * kProlongRows;
+        const int nrow = min(kProlongRows, f.nr - i0);
+        const int j = (p % strips) * 256 + threadIdx.x;
+        __syncthreads();  // the previous piece's rows have been read
+        if (threadIdx.x < 2 * kProlongRows) {
+            const int r = threadIdx.x % kProlongRows;
+            const bool edge = threadIdx.x >= kProlongRows;
+            if (r < nrow) rw[edge][r] = axis_w(i0 + r, a.fr, c.nr, edge);
+        }
+        __syncthreads();
+        if (j >= f.nt) continue;
+        const AxisW tc = axis_w(j, a.ft, c.nt, false), te = axis_w(j, a.ft, c.nt, true);
+        const int64_t o0 = f.uoff + (int64_t)i0 * f.nt + j;
+        for (int r = 0; r < nrow; ++r) {
+            const AxisW rc = rw[0][r], re = rw[1][r];
+            const int64_t o = o0 + (int64_t)r * f.nt;
+            T qx[4], qt[4], qp[4];
+            if constexpr (HAS_U) {
+                load_quad(a.u_c, c, re, tc, qx);
+                load_quad(a.u_c + a.len_c, c, rc, te, qt);
             }
-            if (a.phi_f) a.phi_f[o] = T(blend(a.phi_c, c, rc, tc));
+            if constexpr (HAS_PHI) load_quad(a.phi_c, c, rc, tc, qp);
+            if constexpr (HAS_U) {
+                a.u_f[o] = T(blend(qx, re, tc));
+                a.u_f[a.len_f + o] = T(blend(qt, rc, te));
+            }
+            if constexpr (HAS_PHI) a.phi_f[o] = T(blend(qp, rc, tc));
         }
     }
 }
@@ -758,7 +855,13 @@ void launch_restrict(const XferArgs<T>& a, int ngather, int blocks, hipStream_t 
 template <typename T>
 void launch_prolong(const XferArgs<T>& a, int ngather, int blocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_prolong<T>, dim3(blocks, ngather), dim3(256), 0, stream, a);
+    // one kernel per set of outputs, so that no branch separates a row's loads
+    if (a.u_f && a.phi_f)
+        hipLaunchKernelGGL((k_prolong<T, true, true>), dim3(blocks, ngather), dim3(256), 0, stream, a);
+    else if (a.u_f)
+        hipLaunchKernelGGL((k_prolong<T, true, false>), dim3(blocks, ngather), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_prolong<T, false, true>), dim3(blocks, ngather), dim3(256), 0, stream, a);
 }
 
 void launch_zero_counter(int32_t* counter, hipStream_t stream)
