@@ -96,6 +96,47 @@ def test_prolong_matches_oracle(precision, fr, ft):
     coarse.close()
 
 
+@pytest.mark.parametrize("precision", [E.F32, E.F64])
+@pytest.mark.parametrize("fr,ft", [(1, 2), (2, 3)])
+def test_prolong_wide_gather_and_single_outputs(precision, fr, ft):
+    # a 20 x 5000 gather has more 16-row by 256-sample pieces (20 x 2) than the launch
+    # has blocks per gather (its 20 rows), so blocks take several pieces in turn; the
+    # u-only and phi-only calls give the fields of the call with both outputs
+    dtype = np.float64 if precision == E.F64 else np.float32
+    gs = to_precision([random_small_pair(20, 5000, 31), random_small_pair(9, 300, 32)], dtype)
+    fine, coarse, pcal, pobs, desc, cd = _plans(gs, precision, fr, ft)
+    rng = np.random.default_rng(23)
+    n_c = coarse.batch_len
+    u_c_h = rng.normal(size=(2, n_c)).astype(dtype)
+    phi_c_h = rng.normal(size=n_c).astype(dtype)
+    u_c = torch.from_numpy(u_c_h).to(coarse.device)
+    phi_c = torch.from_numpy(phi_c_h).to(coarse.device)
+    u_f, phi_f = E.prolong(coarse, fine, fr, ft, u_c, phi_c)
+    L = E._lib
+    u_only, phi_only = fine.empty(2), fine.empty()
+    with torch.cuda.device(fine.device):
+        L.check(L.load().emd_prolong(coarse.handle, fine.handle, fr, ft, u_c.data_ptr(), None,
+                                     u_only.data_ptr(), None, None))
+        L.check(L.load().emd_prolong(coarse.handle, fine.handle, fr, ft, None, phi_c.data_ptr(), None,
+                                     phi_only.data_ptr(), None))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u_only.cpu().numpy(), u_f.cpu().numpy())
+    np.testing.assert_array_equal(phi_only.cpu().numpy(), phi_f.cpu().numpy())
+    us = unpack(u_f.cpu().numpy(), desc, 2)
+    phis = unpack(phi_f.cpu().numpy(), desc)
+    ucs = unpack(u_c_h, cd, 2)
+    phics = unpack(phi_c_h, cd)
+    for k, g in enumerate(gs):
+        rx, rt, rp = oracle.prolong(ucs[k][0], ucs[k][1], phics[k], g.nr, g.nt, fr, ft)
+        for got, ref in ((us[k][0], rx), (us[k][1], rt), (phis[k], rp)):
+            if precision == E.F64:
+                np.testing.assert_array_equal(got, ref)
+            else:
+                np.testing.assert_allclose(got, ref, rtol=0, atol=4e-7 * max(1.0, np.abs(ref).max()))
+    fine.close()
+    coarse.close()
+
+
 def test_transfer_rejects_mismatched_plans():
     gs = ragged(np.float32)
     fine, coarse, pcal, pobs, desc, cd = _plans(gs, E.F32, 2, 4)
