@@ -196,6 +196,8 @@ def main():
                     help="coarse levels that start the timed solve, finest first, each grouping FR "
                          "receivers by FT samples of the level above ('none': a plain solve; 'auto': "
                          "1x4,2x4 for c5, else 1x2,1x2,1x2)")
+    ap.add_argument("--coarse-rows", default="8", metavar="ROWS[,ROWS...]",
+                    help="tile height of the coarse levels: one for all, or one per level, finest first")
     ap.add_argument("--coarse-tol-factor", type=float, default=1.0,
                     help="stop rule of the coarse levels over the fine one's")
     ap.add_argument("--fine-only-steps", type=int, default=1,
@@ -271,7 +273,10 @@ def main():
             "emd": torch.empty(len(gathers), dtype=torch.float64, device=dev),
             "info": torch.empty(len(gathers) * E.INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
     levels = parse_levels(args.coarse, args.workload)
-    mg = E.Multigrid(plan, levels, coarse_tol_factor=args.coarse_tol_factor) if levels else None
+    crows = [int(v) for v in args.coarse_rows.split(",")]
+    crows = crows[0] if len(crows) == 1 else crows
+    mg = (E.Multigrid(plan, levels, coarse_rows=crows, coarse_tol_factor=args.coarse_tol_factor)
+          if levels else None)
 
     # Accuracy gate (untimed): the FP32 EMD of the first gathers at the stop rule
     # against FP64 solves of them taken far past it.  If the gate fails, the stop rule
@@ -334,6 +339,10 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
     value = cell_updates / (ms / 1e3)
+    # the last step's time in sweeps per level, the fine grid first, then the coarse
+    # levels finest first (HIP events the library records)
+    level_ms = [round(p.query()["last_sweep_ms"], 1)
+                for p in [plan] + ([lv[0] for lv in mg.levels] if mg is not None else [])]
     inf = E.info_numpy(info)
     emd32 = emd.cpu().numpy().copy()
     if gate is not None:
@@ -648,6 +657,8 @@ def main():
                       "linesearch": args.ls,
                       "coarse_levels": ",".join(f"{a}x{b}" for a, b in levels) or "none",
                       "coarse_stop_rule": f"{args.tol * args.coarse_tol_factor:g}" if levels else None,
+                      "coarse_tile_rows": crows if levels else None,
+                      "sweep_ms_per_level": level_ms,
                       "fine_iters_mean": float(inf["iters"].mean()), "fine_iters_max": int(inf["iters"].max()),
                       "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mg.last_info]
                       if mg is not None else [],

@@ -14,6 +14,7 @@ import hashlib
 import json
 import os
 from dataclasses import dataclass, fields
+from typing import Sequence
 
 import numpy as np
 import torch
@@ -442,7 +443,8 @@ class Multigrid:
     coarse level never uses mass mode `none` (block means over the ragged last
     blocks shift the two masses slightly, and a coarse level only supplies a start),
     it balances the masses instead.  `coarse_rows` is the tile height of the coarse
-    plans (None: the library's default): a coarse batch is a few times smaller than
+    plans, one height for all or one per level in the order of `factors` (None: the
+    library's default): a coarse batch is a few times smaller than
     the fine one, so more of its sweeps run with only its slowest gathers left, and
     there a shorter tile gives more, shorter-lived waves.  `coarse_tol_factor`
     scales the coarse levels' stop rule (tol_res) against the one of their
@@ -450,7 +452,7 @@ class Multigrid:
     takes to its own rule."""
 
     def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None,
-                 coarse_rows: int | None = 8, coarse_tol_factor: float = 1.0):
+                 coarse_rows: int | Sequence[int] | None = 8, coarse_tol_factor: float = 1.0):
         self.fine = plan
         self.levels = []  # (coarse plan, fr, ft), finest first
         prm = params or plan.params
@@ -460,11 +462,18 @@ class Multigrid:
             raise ValueError("coarse_tol_factor must be > 0")
         prm = dataclasses.replace(prm, tol_res=prm.tol_res * float(coarse_tol_factor))
         descs = plan.descs
-        for fr, ft in factors:
+        factors = list(factors)
+        if coarse_rows is None or isinstance(coarse_rows, int):
+            rows = [coarse_rows] * len(factors)
+        else:
+            rows = list(coarse_rows)
+            if len(rows) != len(factors):
+                raise ValueError("coarse_rows needs one tile height per level")
+        for (fr, ft), r in zip(factors, rows):
             cd, n = coarse_descs(descs, int(fr), int(ft))
             cp = Plan(cd, n, prm, device=plan.device)
-            if coarse_rows:
-                cp.set_tiling(int(coarse_rows))
+            if r:
+                cp.set_tiling(int(r))
             self.levels.append((cp, int(fr), int(ft)))
             descs = cd
         self.last_info = []  # per level, coarsest first: the solve info of the last start()

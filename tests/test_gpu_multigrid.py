@@ -280,11 +280,16 @@ def test_multigrid_coarse_level_settings():
     plan, pcal, pobs, desc = make_plan(gs, p)
     with pytest.raises(ValueError):
         E.Multigrid(plan, ((1, 2),), coarse_tol_factor=0.0)
+    with pytest.raises(ValueError, match="one tile height per level"):
+        E.Multigrid(plan, ((1, 2), (1, 2)), coarse_rows=[8])
     plain = E.Multigrid(plan, ((1, 2),), coarse_rows=None)
     q16 = plain.levels[0][0].query()
     assert q16["rows_per_tile"] == 16
     assert plain.levels[0][0].params.tol_res == p.tol_res
     plain.close()
+    per_level = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_rows=[12, 4])
+    assert [cp.query()["rows_per_tile"] for cp, _, _ in per_level.levels] == [12, 4]
+    per_level.close()
     mg = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_tol_factor=1.5)
     for cp, _, _ in mg.levels:
         assert cp.params.tol_res == pytest.approx(1.5e-5, rel=1e-15)
