@@ -198,6 +198,9 @@ def main():
                          "1x4,2x4 for c5, else 1x2,1x2,1x2)")
     ap.add_argument("--coarse-rows", default="8", metavar="ROWS[,ROWS...]",
                     help="tile height of the coarse levels: one for all, or one per level, finest first")
+    ap.add_argument("--coarse-fixed-ips", type=int, default=3, choices=(0, 2, 3),
+                    help="iterations per sweep of the fixed-step coarse levels in the legs that start "
+                         "the linesearch solve from them (0: skip those legs)")
     ap.add_argument("--coarse-tol-factor", type=float, default=1.0,
                     help="stop rule of the coarse levels over the fine one's")
     ap.add_argument("--fine-only-steps", type=int, default=1,
@@ -614,6 +617,30 @@ def main():
                 f"fine iters mean {inf5['iters'].mean():.0f} max {inf5['iters'].max()}, "
                 f"statuses {np.bincount(inf5['status'], minlength=7).tolist()}")
             mg5.close()
+            if args.coarse_fixed_ips > 0:
+                # the same misfit with the coarse levels solved by plain fixed-step PDHG
+                emd5 = b5f["emd"].cpu().numpy().copy()
+                mg5h = E.Multigrid(plan5f, lv5, coarse_tol_factor=args.coarse_tol_factor,
+                                   coarse_iters_per_sweep=args.coarse_fixed_ips)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                _, info5h = run_step(E, plan5f, pc5, po5, b5f, mg5h)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms5h = e0.elapsed_time(e1)
+                inf5h = E.info_numpy(info5h)
+                rel5 = np.abs(b5f["emd"].cpu().numpy() / emd5 - 1)
+                extra["large_full_misfit_fixed_step_coarse"] = {
+                    "what": f"the same misfit, the coarse levels solved by plain PDHG with fixed steps, "
+                            f"{args.coarse_fixed_ips} iterations per sweep, one run",
+                    "ms": round(ms5h, 1), "speedup_vs_linesearch_coarse": round(ms5f / ms5h, 3),
+                    "fine_iters_mean": float(inf5h["iters"].mean()), "fine_iters_max": int(inf5h["iters"].max()),
+                    "coarse_iters_max": [int(E.info_numpy(i)["iters"].max()) for i in mg5h.last_info],
+                    "statuses": np.bincount(inf5h["status"], minlength=7).tolist(),
+                    "emd_rel_diff_vs_linesearch_coarse_max": float(rel5.max())}
+                log(f"16 x 4000 x 1600, fixed-step coarse levels: {ms5h / 1e3:.2f} s ({ms5f / ms5h:.2f}x), "
+                    f"EMD rel diff max {rel5.max():.2e}")
+                mg5h.close()
             plan5f.close()
             del b5f
         del pc5, po5
@@ -647,6 +674,38 @@ def main():
                 np.max(np.abs(emd_o.cpu().numpy()[:len(ref)] / ref - 1)))
         log(f"cold fine start: {stepo:.1f} ms/step (the coarse start is {stepo / ms_per_step:.2f}x faster), "
             f"iters mean {io['iters'].mean():.0f}, EMD rel diff vs coarse start max {rel_o.max():.2e}")
+
+    if args.coarse_fixed_ips > 0 and mg is not None:
+        # the same linesearch solve on the fine grid, started from coarse levels solved
+        # by plain PDHG with fixed steps, K iterations per sweep: a coarse level only
+        # supplies a start, and the fixed-step sweeps move fewer bytes per iteration
+        Kc = args.coarse_fixed_ips
+        mgh = E.Multigrid(plan, levels, coarse_tol_factor=args.coarse_tol_factor, coarse_iters_per_sweep=Kc)
+        run_step(E, plan, pcal, pobs, bufs, mgh)  # captures the coarse plans' graphs
+        torch.cuda.synchronize()
+        e0.record(stream)
+        emd_h, info_h = run_step(E, plan, pcal, pobs, bufs, mgh)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        steph = e0.elapsed_time(e1)
+        ih = E.info_numpy(info_h)
+        rel_h = np.abs(emd_h.cpu().numpy() / emd32 - 1)
+        extra["fixed_step_coarse_start"] = {
+            "what": f"the same linesearch solve on the fine grid, its coarse levels solved by plain PDHG "
+                    f"with fixed steps, {Kc} iterations per sweep", "ms_per_step": round(steph, 3),
+            "speedup_vs_linesearch_coarse": round(ms_per_step / steph, 3),
+            "sweep_ms_per_level": [round(p.query()["last_sweep_ms"], 1)
+                                   for p in [plan] + [lv[0] for lv in mgh.levels]],
+            "fine_iters_mean": float(ih["iters"].mean()), "fine_iters_max": int(ih["iters"].max()),
+            "coarse_iters_mean": [float(E.info_numpy(i)["iters"].mean()) for i in mgh.last_info],
+            "statuses": np.bincount(ih["status"], minlength=7).tolist(),
+            "emd_rel_diff_vs_linesearch_coarse_max": float(rel_h.max())}
+        if ref is not None:
+            extra["fixed_step_coarse_start"]["emd_rel_err_vs_ref_max"] = float(
+                np.max(np.abs(emd_h.cpu().numpy()[:len(ref)] / ref - 1)))
+        log(f"fixed-step coarse start: {steph:.1f} ms/step ({ms_per_step / steph:.2f}x), "
+            f"EMD rel diff vs linesearch coarse levels max {rel_h.max():.2e}")
+        mgh.close()
 
     out = {"metric": "PDHG cell-updates/s to 1e-5 rel EMD err, batched FP32 vs plain FP64; % HBM peak",
            "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,

@@ -444,15 +444,19 @@ class Multigrid:
     blocks shift the two masses slightly, and a coarse level only supplies a start),
     it balances the masses instead.  `coarse_rows` is the tile height of the coarse
     plans, one height for all or one per level in the order of `factors` (None: the
-    library's default): a coarse batch is a few times smaller than
-    the fine one, so more of its sweeps run with only its slowest gathers left, and
-    there a shorter tile gives more, shorter-lived waves.  `coarse_tol_factor`
-    scales the coarse levels' stop rule (tol_res) against the one of their
-    parameters: a coarse level only supplies a start, which the fine solve then
-    takes to its own rule."""
+    library's default; "auto": 8 rows, or the default 16 for fixed-step levels): a
+    coarse batch is a few times smaller than the fine one, so more of its sweeps run
+    with only its slowest gathers left, and there a shorter tile gives more,
+    shorter-lived waves.  `coarse_tol_factor` scales the coarse levels' stop rule
+    (tol_res) against the one of their parameters: a coarse level only supplies a
+    start, which the fine solve then takes to its own rule.  `coarse_iters_per_sweep`
+    = K (2 or 3) solves the coarse levels by plain PDHG with the fixed steps of
+    Section 2.2, K iterations per pass over the fields (stop rule checked every 3K
+    iterations), whatever method the fine plan uses: a cheaper start."""
 
     def __init__(self, plan: Plan, factors=((1, 4),), params: SolverParams | None = None,
-                 coarse_rows: int | Sequence[int] | None = 8, coarse_tol_factor: float = 1.0):
+                 coarse_rows: int | Sequence[int] | str | None = "auto", coarse_tol_factor: float = 1.0,
+                 coarse_iters_per_sweep: int = 0):
         self.fine = plan
         self.levels = []  # (coarse plan, fr, ft), finest first
         prm = params or plan.params
@@ -461,6 +465,15 @@ class Multigrid:
         if not coarse_tol_factor > 0:
             raise ValueError("coarse_tol_factor must be > 0")
         prm = dataclasses.replace(prm, tol_res=prm.tol_res * float(coarse_tol_factor))
+        k = int(coarse_iters_per_sweep)
+        if k:
+            if k not in (2, 3):
+                raise ValueError("coarse_iters_per_sweep must be 0, 2 or 3")
+            prm = dataclasses.replace(prm, ls_mode=L.LS_FIXED, iters_per_sweep=k, check_every=3 * k)
+        if isinstance(coarse_rows, str):
+            if coarse_rows != "auto":
+                raise ValueError('coarse_rows must be a height, a list of heights, None or "auto"')
+            coarse_rows = None if k else 8
         descs = plan.descs
         factors = list(factors)
         if coarse_rows is None or isinstance(coarse_rows, int):

@@ -156,9 +156,11 @@ def test_transfer_rejects_mismatched_plans():
         pl.close()
 
 
+@pytest.mark.parametrize("coarse_ips", [0, 2])
 @pytest.mark.parametrize("factors", [((1, 2),), ((2, 2), (1, 2))])
-def test_multigrid_solve_reaches_the_cold_optimum(factors):
-    # FP64: the coarse levels only change where the fine solve starts.  The stop rule
+def test_multigrid_solve_reaches_the_cold_optimum(factors, coarse_ips):
+    # FP64: the coarse levels only change where the fine solve starts (also when they
+    # are solved by fixed-step PDHG, two iterations per sweep).  The stop rule
     # certifies feasibility, not optimality (on tiny random grids a 1e-6 residual can
     # leave the transport ~0.5 % above the optimum), so the two solves are compared
     # through their duality brackets: both bracket the same optimum, and their EMDs
@@ -166,7 +168,7 @@ def test_multigrid_solve_reaches_the_cold_optimum(factors):
     gs = ragged(np.float64)
     p = E.SolverParams(precision=E.F64, tol_res=1e-6, max_iter=400000)
     plan, pcal, pobs, desc = make_plan(gs, p)
-    mg = E.Multigrid(plan, factors)
+    mg = E.Multigrid(plan, factors, coarse_iters_per_sweep=coarse_ips)
     emd_w, phi_w, u_w, info_w, mass = mg.solve(pcal, pobs)
     s, mass = E.emd_decompose(plan, pcal, pobs)
     emd_c, phi_c, u_c, info_c = E.emd_pdhg_solve(plan, s, u=plan.empty(2), mass=mass)
@@ -290,6 +292,28 @@ def test_multigrid_coarse_level_settings():
     per_level = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_rows=[12, 4])
     assert [cp.query()["rows_per_tile"] for cp, _, _ in per_level.levels] == [12, 4]
     per_level.close()
+    # fixed-step coarse levels: plain PDHG, three iterations per sweep, the stop rule
+    # every nine, the library's default tile height; the fine plan keeps its method
+    with pytest.raises(ValueError, match="coarse_iters_per_sweep"):
+        E.Multigrid(plan, ((1, 2),), coarse_iters_per_sweep=4)
+    fx = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_iters_per_sweep=3)
+    for cp, _, _ in fx.levels:
+        assert (cp.params.ls_mode, cp.params.iters_per_sweep, cp.params.check_every) == (E.LS_FIXED, 3, 9)
+        assert cp.query()["rows_per_tile"] == 16
+    assert plan.params.ls_mode == p.ls_mode
+    emd_x, _, _, info_x, _ = fx.solve(pcal, pobs)
+    emd_x = emd_x.clone()
+    ls = E.Multigrid(plan, ((1, 2), (1, 2)))
+    ref_emd, _, _, _, _ = ls.solve(pcal, pobs)
+    torch.cuda.synchronize()
+    ls.close()
+    ix = E.info_numpy(info_x)
+    assert np.all(ix["status"] == E.GATHER_STATUS.index("CONVERGED"))
+    for li in fx.last_info:
+        assert np.all(E.info_numpy(li)["rel_res"] <= 1e-5)
+    # seismic-like gathers: at the 1e-5 rule the EMD hardly depends on the start
+    np.testing.assert_allclose(emd_x.cpu().numpy(), ref_emd.cpu().numpy(), rtol=2e-4)
+    fx.close()
     mg = E.Multigrid(plan, ((1, 2), (1, 2)), coarse_tol_factor=1.5)
     for cp, _, _ in mg.levels:
         assert cp.params.tol_res == pytest.approx(1.5e-5, rel=1e-15)
