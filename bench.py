@@ -11,9 +11,11 @@ iterations, divided by the step time) for the batched FP32 solve; the EMD of the
 first gathers is checked against FP64 solves of them taken far past the stop rule
 (the accuracy the metric is quoted at), and the plain FP64 solve of the same gathers,
 one gather per plan, is timed beside it.  Further legs: the solve without the
-coarse start, plain fixed-step PDHG with three iterations per sweep, the 16 x 4000 x
-1600 batch at a fixed budget and its whole misfit to the stop rule, the one-pass
-kernels, and the CPU oracle.
+coarse start, the same linesearch solve started from coarse levels solved by plain
+fixed-step PDHG, plain fixed-step PDHG with three iterations per sweep on every
+level, the 16 x 4000 x 1600 batch at a fixed budget and its whole misfit to the stop
+rule (also from fixed-step coarse levels), the one-pass kernels and grid transfers,
+and the CPU oracle.
 
 Default workload: 64 gathers, nt ~ U{1500..3000}, nr ~ U{200..500}, 4-8 hyperbolic
 events (seed 3).  Prints one JSON line.
