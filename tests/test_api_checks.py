@@ -70,3 +70,16 @@ def test_residual_history_unrolls_the_ring():
     assert h[2].size == 0
     with pytest.raises(RuntimeError):
         A.residual_history(SimpleNamespace(ngather=1, params=plan.params, _hist=None), rec[:1])
+
+
+def test_multigrid_arguments_are_checked_before_any_plan_is_built():
+    # every bad setting raises before a coarse plan (and so the library) is touched
+    fine = SimpleNamespace(params=A.SolverParams(), descs=[(8, 40, 1.0, 0.01, 0)], device=torch.device("cpu"))
+    with pytest.raises(ValueError, match="coarse_tol_factor"):
+        A.Multigrid(fine, ((1, 2),), coarse_tol_factor=0.0)
+    with pytest.raises(ValueError, match="coarse_iters_per_sweep"):
+        A.Multigrid(fine, ((1, 2),), coarse_iters_per_sweep=1)
+    with pytest.raises(ValueError, match="coarse_rows must be"):
+        A.Multigrid(fine, ((1, 2),), coarse_rows="tall")
+    with pytest.raises(ValueError, match="one tile height per level"):
+        A.Multigrid(fine, ((1, 2), (1, 2)), coarse_rows=[8, 8, 8])
