@@ -682,7 +682,10 @@ def main():
         # by plain PDHG with fixed steps, K iterations per sweep: a coarse level only
         # supplies a start, and the fixed-step sweeps move fewer bytes per iteration
         Kc = args.coarse_fixed_ips
-        mgh = E.Multigrid(plan, levels, coarse_tol_factor=args.coarse_tol_factor, coarse_iters_per_sweep=Kc)
+        # coarse levels at the rule the headline's coarse levels use (a failed gate
+        # tightens only the fine plan's)
+        mgh = E.Multigrid(plan, levels, params=dataclasses.replace(params, tol_res=args.tol),
+                          coarse_tol_factor=args.coarse_tol_factor, coarse_iters_per_sweep=Kc)
         run_step(E, plan, pcal, pobs, bufs, mgh)  # captures the coarse plans' graphs
         torch.cuda.synchronize()
         e0.record(stream)
