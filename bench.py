@@ -95,7 +95,9 @@ def step_stats(plan, mg=None):
 
 def parse_levels(spec, workload_name):
     if spec == "auto":
-        spec = "1x4,2x4" if workload_name == "c5" else "1x2,1x2,1x2"
+        # a single small gather's coarse sweeps are as latency-bound as its fine ones,
+        # so it is solved without a coarse start
+        spec = {"c5": "1x4,2x4", "c2": "none"}.get(workload_name, "1x2,1x2,1x2")
     if spec == "none":
         return []
     return [tuple(int(v) for v in f.split("x")) for f in spec.split(",")]
@@ -197,7 +199,7 @@ def main():
     ap.add_argument("--coarse", default="auto", metavar="FRxFT[,FRxFT...]",
                     help="coarse levels that start the timed solve, finest first, each grouping FR "
                          "receivers by FT samples of the level above ('none': a plain solve; 'auto': "
-                         "1x4,2x4 for c5, else 1x2,1x2,1x2)")
+                         "1x4,2x4 for c5, none for c2, else 1x2,1x2,1x2)")
     ap.add_argument("--coarse-rows", default="8", metavar="ROWS[,ROWS...]",
                     help="tile height of the coarse levels: one for all, or one per level, finest first")
     ap.add_argument("--coarse-fixed-ips", type=int, default=3, choices=(0, 2, 3),
